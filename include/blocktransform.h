@@ -1,0 +1,193 @@
+/*
+ * blocktransform.h -- C ABI of the MI355X (gfx950) block-transform library.
+ *
+ * The operation.  J. Selva's non-iterative type-4/5 NFFT methods reduce every
+ * regular-grid step to one operator: evaluate a filtered trigonometric
+ * polynomial on a uniform grid.  With the kernel coefficients Lambda of
+ * eq. (4) and the coefficient vector S of eq. (34), the polynomial of eq. (6)
+ * read at t = u/N is
+ *
+ *     y_u = sum_{n<N} Lambda_n S_n exp(+j 2 pi n u / N),        u < N.
+ *
+ * Its coset u = M q is eq. (7): a filter multiply, a circular fold of the
+ * length-N spectrum onto K bins and a length-K IDFT (the paper's P is K here,
+ * its oversampling factor eta is M, so N = K*M is its R = eta*P).  Evaluating
+ * all M cosets makes the map square; when no Lambda_n is zero it is inverted
+ * by eq. (31) generalised from the damping filter exp(-2 pi n a) of eq. (8)
+ * to any nonzero real filter:
+ *
+ *     S_n = (N Lambda_n)^{-1} sum_u y_u exp(-j 2 pi n u / N).
+ *
+ * The adjoint is the Hermitian of the forward matrix (the same pairing that
+ * relates the type-4 and type-5 systems, Sec. 6).  DFT signs and
+ * normalisation follow eq. (0); the IDFT carries 1/P, as eq. (7) requires.
+ *
+ * Data layout.  A batch is `nblocks` blocks of N = K*M points.  Complex
+ * arrays are complex64: interleaved (re, im) float32, block-major, natural
+ * index order inside a block ([nblocks][N]).  Taps are float32: either one
+ * shared vector [N] (tap_stride = 0) or one vector per block (tap_stride = N,
+ * [nblocks][N]).
+ *
+ * Supported sizes.  K a power of two in [1, 1024]; M in [1, 16].  Other
+ * values return TF_EUNSUPPORTED.  nblocks = 0 is a valid empty call.
+ *
+ * Ownership and ordering.  Every pointer passed to a transform call is a
+ * device pointer owned by the caller, except the ragged layout arrays given to
+ * transform_ragged_plan_create, which are host arrays copied by the library.
+ * The library allocates only when a (K, M) schedule is first used on a device
+ * (its twiddle table) and when a ragged plan is created; transform calls
+ * themselves never allocate.  All transform calls are asynchronous on
+ * `stream` (a hipStream_t; NULL means the default stream).  Inputs and
+ * outputs must not overlap.
+ *
+ * Errors.  Arguments are validated on the host before any launch; no
+ * exception crosses this interface.  Conditions found on the device (a zero
+ * tap in an inverse) are reported through `status_dev`, and the affected
+ * outputs then hold Inf/NaN by IEEE rules.
+ */
+#ifndef BLOCKTRANSFORM_H
+#define BLOCKTRANSFORM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TF_OK = 0,
+    TF_EINVAL = -1,         /* bad argument: null/overlapping/misaligned pointer, negative size */
+    TF_EUNSUPPORTED = -2,   /* K or M outside the supported set, or unsupported compute mode */
+    TF_ESINGULAR = -3,      /* reserved for host-detected singular filters */
+    TF_EHIP = -4,           /* a HIP runtime call failed (launch, copy, allocation) */
+    TF_EWORKSPACE = -5      /* workspace missing or smaller than transform_workspace_size() */
+} tf_status;
+
+typedef enum {
+    TF_FP32 = 0,            /* fused single-pass kernel, FP32 arithmetic */
+    TF_PLAIN_FP32 = 3,      /* unfused comparison path: one kernel per stage, HBM between stages */
+    TF_SPLIT_BF16 = 1,      /* stage DFTs as BF16 hi+lo MFMA GEMMs, FP32 accumulation */
+    TF_SPLIT_FP16 = 2       /* stage DFTs as scaled FP16 hi+lo MFMA GEMMs, FP32 accumulation */
+} tf_compute;
+
+/*
+ * transform_forward -- y = T(S): y_u = sum_n Lambda_n S_n e^{+j 2 pi n u/N}
+ * (eq. (6) on the grid u/N; eq. (7) is its u = M q coset).
+ *   coeffs   in : S, complex64 [nblocks][N]
+ *   taps     in : Lambda, float32 [N] (tap_stride 0) or [nblocks][N] (tap_stride N)
+ *   samples  out: y, complex64 [nblocks][N]
+ *   compute     : a tf_compute value
+ *   workspace   : device scratch of at least transform_workspace_size(...) bytes
+ *                 (0 bytes for TF_FP32; NULL allowed when 0 is required)
+ */
+int transform_forward(const void *coeffs, const float *taps, void *samples,
+                      int64_t nblocks, int32_t K, int32_t M, int64_t tap_stride,
+                      int32_t compute, void *workspace, size_t workspace_bytes,
+                      void *stream);
+
+/*
+ * transform_inverse -- S = T^{-1}(y): S_n = (N Lambda_n)^{-1} sum_u y_u e^{-j 2 pi n u/N}
+ * (eq. (31) with the damping filter of eq. (8) replaced by any nonzero filter).
+ *   samples    in : y, complex64 [nblocks][N]
+ *   coeffs     out: S, complex64 [nblocks][N]
+ *   status_dev out: nullable device int32; the kernel stores 1 into it when it
+ *                   meets a zero tap (it never clears it: zero it first)
+ */
+int transform_inverse(const void *samples, const float *taps, void *coeffs,
+                      int64_t nblocks, int32_t K, int32_t M, int64_t tap_stride,
+                      int32_t compute, int32_t *status_dev,
+                      void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * transform_adjoint -- the Hermitian of the forward, and the filter gradient.
+ *   W_n = sum_u ybar_u e^{-j 2 pi n u/N};   Sbar_n = Lambda_n W_n;
+ *   Lambdabar_n = Re(conj(S_n) W_n), summed over blocks when taps are shared.
+ *   samples_bar in : ybar, complex64 [nblocks][N]
+ *   coeffs      in : S, complex64 [nblocks][N]; nullable unless taps_bar is given
+ *   coeffs_bar  out: Sbar, complex64 [nblocks][N]
+ *   taps_bar    out: nullable; float32 [N] (shared) or [nblocks][N] (per block).
+ *                    The shared reduction is deterministic (fixed summation
+ *                    order) and needs the workspace.
+ */
+int transform_adjoint(const void *samples_bar, const float *taps, const void *coeffs,
+                      void *coeffs_bar, float *taps_bar,
+                      int64_t nblocks, int32_t K, int32_t M, int64_t tap_stride,
+                      int32_t compute, void *workspace, size_t workspace_bytes,
+                      void *stream);
+
+/*
+ * transform_inverse_adjoint -- the Hermitian of the inverse, and its filter gradient
+ * (what autograd needs behind transform_inverse).
+ *   ybar_u = sum_n e^{+j 2 pi n u/N} gbar_n / (N Lambda_n);
+ *   Lambdabar_n = -Re(conj(gbar_n) Shat_n) / Lambda_n, summed over blocks when shared,
+ *   where Shat is the inverse's output.
+ *   coeffs_bar  in : gbar, complex64 [nblocks][N]
+ *   coeffs      in : Shat, nullable unless taps_bar is given
+ *   samples_bar out: ybar, complex64 [nblocks][N]
+ */
+int transform_inverse_adjoint(const void *coeffs_bar, const float *taps, const void *coeffs,
+                              void *samples_bar, float *taps_bar,
+                              int64_t nblocks, int32_t K, int32_t M, int64_t tap_stride,
+                              int32_t compute, void *workspace, size_t workspace_bytes,
+                              void *stream);
+
+/* Bytes of device workspace a call with these arguments needs (0 when none).
+   `with_tapbar` is 1 when the call computes taps_bar. */
+size_t transform_workspace_size(int64_t nblocks, int32_t K, int32_t M, int64_t tap_stride,
+                                int32_t compute, int32_t with_tapbar);
+
+/* Build the (K, M) schedule's tables on the current device ahead of time
+   (for instance before stream capture).  Synchronous. */
+int transform_prepare(int32_t K, int32_t M, int32_t compute);
+
+/* Human-readable name of a tf_status value (static storage). */
+const char *transform_status_string(int status);
+
+/* ---------------------------------------------------------------- schedules
+ * A (K, M) pair can run under several compiled schedules (radix plan, threads
+ * per block, blocks per workgroup).  The autotuner times them and records the
+ * winner; the choices persist as a small JSON file.
+ */
+
+/* Number of compiled fused schedules for (K, M); 0 when unsupported. */
+int transform_schedule_count(int32_t K, int32_t M);
+
+/* Describe schedule `idx` of (K, M) into `buf` (JSON object text). */
+int transform_schedule_describe(int32_t K, int32_t M, int32_t idx, char *buf, size_t buflen);
+
+/* Select schedule `idx` for (K, M) on all devices (idx -1: back to the default)
+   and the grid cap in workgroups (0: automatic). */
+int transform_schedule_select(int32_t K, int32_t M, int32_t idx, int32_t grid_cap);
+
+/* Load / save the selections as JSON ({"K,M": [idx, grid_cap], ...}). */
+int transform_load_schedule(const char *json_path);
+int transform_save_schedule(const char *json_path);
+
+/* ---------------------------------------------------------------- ragged batches
+ * A ragged batch is nblocks blocks with their own (K_b, M_b); block b's
+ * points live at complex offset x_off[b] of the flat arrays and its taps at
+ * float offset tap_off[b] (per-block taps only).  The plan sorts the blocks
+ * by cost into a work list that one persistent kernel drains through an
+ * atomic queue.  K_b, M_b follow the uniform limits, with N_b = K_b M_b <= 16384.
+ */
+typedef struct tf_ragged_plan_s *tf_ragged_plan;
+
+/* Build a plan on the current device from host arrays of length nblocks.
+   `total_points` is the length of the flat complex arrays.  Allocates. */
+int transform_ragged_plan_create(const int32_t *K, const int32_t *M, const int64_t *x_off,
+                                 const int64_t *tap_off, int64_t nblocks, int64_t total_points,
+                                 tf_ragged_plan *plan);
+int transform_ragged_plan_destroy(tf_ragged_plan plan);
+
+/* direction: 0 forward, 1 inverse, 2 adjoint (taps_bar per block, nullable; needs aux = S).
+   `use_graph` replays a HIP graph captured on first use for these pointers. */
+int transform_ragged_execute(tf_ragged_plan plan, int32_t direction, const void *in,
+                             const float *taps, void *out, const void *aux, float *taps_bar,
+                             int32_t *status_dev, int32_t use_graph, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BLOCKTRANSFORM_H */

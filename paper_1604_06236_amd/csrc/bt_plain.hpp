@@ -1,0 +1,33 @@
+// Unfused comparison path and the tap-gradient row reduction (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bt_dft.hpp"
+
+namespace bt {
+
+struct PlainArgs {
+    int K, M;
+    int64_t nblocks;
+    int64_t tap_stride;
+    const float *taps;
+    const c32 *roots;     // e^{+j 2 pi k / N}, k < N
+    const c32 *aux;       // S for the tap term of the adjoint
+    c32 *out;
+    int *status;
+    int conj_io, in_op, out_op, tg_op;
+};
+
+// runs all stages; ws0 and ws1 each hold nblocks*N complex values; tg_part
+// receives per-block tap-gradient rows when tg_op is set
+hipError_t plain_run(const PlainArgs &a, const c32 *in, c32 *ws0, c32 *ws1, float *tg_part,
+                     hipStream_t s);
+
+// out[k] = sum_{r < rows} part[r*n + k], fixed order; `scratch` holds
+// ceil(rows/64)*n floats
+hipError_t rows_reduce(const float *part, int64_t rows, int64_t n, float *scratch, float *out,
+                       hipStream_t s);
+
+} // namespace bt

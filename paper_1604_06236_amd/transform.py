@@ -1,0 +1,215 @@
+"""Python binding of the block transform: the C-ABI entry points on torch tensors.
+
+Argument marshalling only: every arithmetic step runs in the HIP library.
+torch supplies device memory (outputs, workspace) and the current stream.
+
+Shapes: coefficient / sample tensors are complex64 [B, N] (N = K*M), taps are
+float32 [N] (shared) or [B, N] (one filter per block), all contiguous on the
+same GPU.  The operators (per block, omega = exp(j 2 pi / N)):
+
+  transform_forward          y_u  = sum_n taps_n S_n omega^{+nu}          (eq. (6) on u/N; eq. (7) at u = Mq)
+  transform_inverse          S_n  = (N taps_n)^{-1} sum_u y_u omega^{-nu}  (eq. (31), any nonzero filter)
+  transform_adjoint          Sbar = taps . W,  tapbar = Re(conj(S) W),  W_n = sum_u ybar_u omega^{-nu}
+  transform_inverse_adjoint  ybar_u = sum_n omega^{+nu} g_n/(N taps_n),  tapbar = -Re(conj(g) Shat)/taps
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Tuple
+
+import torch
+
+from . import _native as nat
+
+__all__ = [
+    "transform_forward", "transform_inverse", "transform_adjoint", "transform_inverse_adjoint",
+    "transform_prepare", "workspace_size", "schedules", "select_schedule", "Transform",
+    "InverseTransform", "forward", "inverse",
+]
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device: torch.device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _compute(c) -> int:
+    return nat.COMPUTE[c] if isinstance(c, str) else int(c)
+
+
+def _check_blocks(x: torch.Tensor, name: str, K: int, M: int) -> int:
+    if not x.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if x.dtype != torch.complex64:
+        raise TypeError(f"{name} must be complex64, got {x.dtype}")
+    if x.dim() != 2 or x.shape[1] != K * M:
+        raise ValueError(f"{name} must be [B, {K * M}], got {tuple(x.shape)}")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return x.shape[0]
+
+
+def _tap_stride(taps: torch.Tensor, B: int, N: int, device) -> int:
+    if taps.dtype != torch.float32 or not taps.is_contiguous() or taps.device != device:
+        raise ValueError("taps must be contiguous float32 on the same device")
+    if taps.shape == (N,):
+        return 0
+    if taps.shape == (B, N):
+        return N
+    raise ValueError(f"taps must be [{N}] or [{B}, {N}], got {tuple(taps.shape)}")
+
+
+def workspace_size(B: int, K: int, M: int, tap_stride: int, compute="fp32", with_tapbar=False) -> int:
+    return int(nat.load().transform_workspace_size(B, K, M, tap_stride, _compute(compute),
+                                                   1 if with_tapbar else 0))
+
+
+def _workspace(B, K, M, tap_stride, compute, with_tapbar, device):
+    n = workspace_size(B, K, M, tap_stride, compute, with_tapbar)
+    if n == 0:
+        return None, 0
+    return torch.empty(n, dtype=torch.uint8, device=device), n
+
+
+def transform_prepare(K: int, M: int, compute="fp32"):
+    nat.check("transform_prepare", nat.load().transform_prepare(K, M, _compute(compute)))
+
+
+def transform_forward(coeffs: torch.Tensor, taps: torch.Tensor, K: int, M: int, *,
+                      out: Optional[torch.Tensor] = None, compute="fp32") -> torch.Tensor:
+    B = _check_blocks(coeffs, "coeffs", K, M)
+    ts = _tap_stride(taps, B, K * M, coeffs.device)
+    out = torch.empty_like(coeffs) if out is None else out
+    _check_blocks(out, "samples", K, M)
+    ws, wsb = _workspace(B, K, M, ts, compute, False, coeffs.device)
+    nat.check("transform_forward", nat.load().transform_forward(
+        _ptr(coeffs), _ptr(taps), _ptr(out), B, K, M, ts, _compute(compute), _ptr(ws), wsb,
+        _stream(coeffs.device)))
+    return out
+
+
+def transform_inverse(samples: torch.Tensor, taps: torch.Tensor, K: int, M: int, *,
+                      out: Optional[torch.Tensor] = None, status: Optional[torch.Tensor] = None,
+                      compute="fp32") -> torch.Tensor:
+    """`status` (int32 [1], zeroed by the caller) is set to 1 when a zero tap is met."""
+    B = _check_blocks(samples, "samples", K, M)
+    ts = _tap_stride(taps, B, K * M, samples.device)
+    out = torch.empty_like(samples) if out is None else out
+    _check_blocks(out, "coeffs", K, M)
+    if status is not None and (status.dtype != torch.int32 or status.device != samples.device):
+        raise ValueError("status must be an int32 tensor on the same device")
+    ws, wsb = _workspace(B, K, M, ts, compute, False, samples.device)
+    nat.check("transform_inverse", nat.load().transform_inverse(
+        _ptr(samples), _ptr(taps), _ptr(out), B, K, M, ts, _compute(compute), _ptr(status),
+        _ptr(ws), wsb, _stream(samples.device)))
+    return out
+
+
+def transform_adjoint(samples_bar: torch.Tensor, taps: torch.Tensor, K: int, M: int, *,
+                      coeffs: Optional[torch.Tensor] = None, want_taps_bar: bool = False,
+                      out: Optional[torch.Tensor] = None, taps_bar: Optional[torch.Tensor] = None,
+                      compute="fp32") -> Tuple[torch.Tensor, Optional[torch.Tensor]]:
+    B = _check_blocks(samples_bar, "samples_bar", K, M)
+    N = K * M
+    ts = _tap_stride(taps, B, N, samples_bar.device)
+    out = torch.empty_like(samples_bar) if out is None else out
+    _check_blocks(out, "coeffs_bar", K, M)
+    tb = None
+    if want_taps_bar or taps_bar is not None:
+        if coeffs is None:
+            raise ValueError("the tap gradient needs coeffs")
+        _check_blocks(coeffs, "coeffs", K, M)
+        tb = taps_bar if taps_bar is not None else torch.empty(
+            (N,) if ts == 0 else (B, N), dtype=torch.float32, device=samples_bar.device)
+    ws, wsb = _workspace(B, K, M, ts, compute, tb is not None, samples_bar.device)
+    nat.check("transform_adjoint", nat.load().transform_adjoint(
+        _ptr(samples_bar), _ptr(taps), _ptr(coeffs), _ptr(out), _ptr(tb), B, K, M, ts,
+        _compute(compute), _ptr(ws), wsb, _stream(samples_bar.device)))
+    return out, tb
+
+
+def transform_inverse_adjoint(coeffs_bar: torch.Tensor, taps: torch.Tensor, K: int, M: int, *,
+                              coeffs: Optional[torch.Tensor] = None, want_taps_bar: bool = False,
+                              out: Optional[torch.Tensor] = None,
+                              compute="fp32") -> Tuple[torch.Tensor, Optional[torch.Tensor]]:
+    B = _check_blocks(coeffs_bar, "coeffs_bar", K, M)
+    N = K * M
+    ts = _tap_stride(taps, B, N, coeffs_bar.device)
+    out = torch.empty_like(coeffs_bar) if out is None else out
+    tb = None
+    if want_taps_bar:
+        if coeffs is None:
+            raise ValueError("the tap gradient needs the inverse's output (coeffs)")
+        _check_blocks(coeffs, "coeffs", K, M)
+        tb = torch.empty((N,) if ts == 0 else (B, N), dtype=torch.float32, device=coeffs_bar.device)
+    ws, wsb = _workspace(B, K, M, ts, compute, tb is not None, coeffs_bar.device)
+    nat.check("transform_inverse_adjoint", nat.load().transform_inverse_adjoint(
+        _ptr(coeffs_bar), _ptr(taps), _ptr(coeffs), _ptr(out), _ptr(tb), B, K, M, ts,
+        _compute(compute), _ptr(ws), wsb, _stream(coeffs_bar.device)))
+    return out, tb
+
+
+# ------------------------------------------------------------------ schedules
+def schedules(K: int, M: int):
+    import json
+    lib = nat.load()
+    out = []
+    buf = ctypes.create_string_buffer(512)
+    for i in range(lib.transform_schedule_count(K, M)):
+        nat.check("transform_schedule_describe", lib.transform_schedule_describe(K, M, i, buf, 512))
+        out.append(json.loads(buf.value.decode()))
+    return out
+
+
+def select_schedule(K: int, M: int, idx: int, grid_cap: int = 0):
+    nat.check("transform_schedule_select", nat.load().transform_schedule_select(K, M, idx, grid_cap))
+
+
+# ------------------------------------------------------------------ autograd
+class Transform(torch.autograd.Function):
+    """y = T_taps(S); gradients through the adjoint kernel (PyTorch's convention:
+    grad_S = T^H grad_y, grad_taps = Re(conj(S) . W))."""
+
+    @staticmethod
+    def forward(ctx, S, taps, K, M):
+        ctx.K, ctx.M = K, M
+        ctx.save_for_backward(S, taps)
+        return transform_forward(S.contiguous(), taps.contiguous(), K, M)
+
+    @staticmethod
+    def backward(ctx, gy):
+        S, taps = ctx.saved_tensors
+        need_taps = ctx.needs_input_grad[1]
+        gS, gt = transform_adjoint(gy.contiguous(), taps, ctx.K, ctx.M,
+                                   coeffs=S if need_taps else None, want_taps_bar=need_taps)
+        return (gS if ctx.needs_input_grad[0] else None), gt, None, None
+
+
+class InverseTransform(torch.autograd.Function):
+    """S = T_taps^{-1}(y); gradients through the inverse's adjoint kernel."""
+
+    @staticmethod
+    def forward(ctx, y, taps, K, M):
+        ctx.K, ctx.M = K, M
+        S = transform_inverse(y.contiguous(), taps.contiguous(), K, M)
+        ctx.save_for_backward(taps, S)
+        return S
+
+    @staticmethod
+    def backward(ctx, gS):
+        taps, S = ctx.saved_tensors
+        need_taps = ctx.needs_input_grad[1]
+        gy, gt = transform_inverse_adjoint(gS.contiguous(), taps, ctx.K, ctx.M,
+                                           coeffs=S if need_taps else None, want_taps_bar=need_taps)
+        return (gy if ctx.needs_input_grad[0] else None), gt, None, None
+
+
+def forward(S, taps, K, M):
+    return Transform.apply(S, taps, K, M)
+
+
+def inverse(y, taps, K, M):
+    return InverseTransform.apply(y, taps, K, M)

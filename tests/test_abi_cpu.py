@@ -1,0 +1,113 @@
+"""The C-ABI library loads, exports every declared symbol, and validates
+arguments on the host (no GPU needed: none of these calls reaches a launch)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1604_06236_amd import _native as nat
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "blocktransform.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(transform_\w+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(nat.LIB_PATH):
+        from paper_1604_06236_amd import build
+        build.build(force=False)
+    return nat.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_symbols()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in nat.EXPORTED, n
+
+
+def test_status_strings(lib):
+    for s in (0, -1, -2, -3, -4, -5):
+        assert lib.transform_status_string(s).startswith(b"TF_")
+
+
+def _fwd(lib, B, K, M, ts=0, compute=0, ptr=8):
+    p = ctypes.c_void_p(ptr) if ptr else None
+    q = ctypes.c_void_p(ptr + (1 << 30)) if ptr else None
+    return lib.transform_forward(p, q, ctypes.c_void_p(ptr + (2 << 30)) if ptr else None, B, K, M,
+                                 ts, compute, None, 0, None)
+
+
+def test_host_validation(lib):
+    assert _fwd(lib, 0, 16, 5, ptr=0) == nat.TF_OK                 # empty batch
+    assert _fwd(lib, -1, 16, 5) == nat.TF_EINVAL
+    for K, M in ((3, 5), (2048, 1), (0, 4), (16, 0), (16, 17)):
+        assert _fwd(lib, 4, K, M) == nat.TF_EUNSUPPORTED, (K, M)
+    assert _fwd(lib, 4, 16, 5, ptr=0) == nat.TF_EINVAL              # null pointers
+    assert _fwd(lib, 4, 16, 5, ts=7) == nat.TF_EINVAL               # tap stride not 0 or N
+    assert _fwd(lib, 4, 16, 5, ptr=12) == nat.TF_EINVAL             # misaligned complex pointer
+    assert _fwd(lib, 4, 16, 5, compute=9) == nat.TF_EUNSUPPORTED
+    # overlapping input and output
+    p = ctypes.c_void_p(1 << 20)
+    t = ctypes.c_void_p(1 << 32)
+    assert lib.transform_forward(p, t, ctypes.c_void_p((1 << 20) + 64), 4, 16, 5, 0, 0, None, 0,
+                                 None) == nat.TF_EINVAL
+    # the tap gradient needs the coefficients
+    assert lib.transform_adjoint(ctypes.c_void_p(1 << 20), t, None, ctypes.c_void_p(1 << 31),
+                                 ctypes.c_void_p(1 << 33), 4, 16, 5, 0, 0, None, 0,
+                                 None) == nat.TF_EINVAL
+
+
+def test_schedule_registry(lib, tmp_path):
+    from paper_1604_06236_amd import transform as T
+    for K in (1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024):
+        for M in range(1, 17):
+            sch = T.schedules(K, M)
+            assert sch, (K, M)
+            for s in sch:
+                prod = 1
+                for r in s["radices"]:
+                    prod *= r
+                assert prod == K * M and s["lds_bytes"] <= 160 * 1024
+    assert lib.transform_schedule_count(3, 3) == 0
+    assert lib.transform_schedule_select(128, 15, 99, 0) == nat.TF_EINVAL
+    assert lib.transform_schedule_select(128, 15, 1, 512) == nat.TF_OK
+    path = str(tmp_path / "sched.json").encode()
+    assert lib.transform_save_schedule(path) == nat.TF_OK
+    assert lib.transform_schedule_select(128, 15, -1, 0) == nat.TF_OK
+    assert lib.transform_load_schedule(path) == nat.TF_OK
+    txt = open(path.decode()).read()
+    assert '"128,15": [-1, 0]' in txt or '"128,15"' in txt
+    assert lib.transform_schedule_select(128, 15, -1, 0) == nat.TF_OK
+
+
+def test_workspace_sizes_host_only(lib):
+    assert lib.transform_workspace_size(10, 16, 5, 0, 0, 0) == 0
+    # plain path: two complex buffers, plus tap-gradient rows when shared
+    assert lib.transform_workspace_size(10, 16, 5, 0, 3, 0) == 2 * 10 * 80 * 8
+    assert lib.transform_workspace_size(10, 16, 5, 0, 3, 1) == 2 * 10 * 80 * 8 + 10 * 80 * 4
+    assert lib.transform_workspace_size(0, 16, 5, 0, 3, 1) == 0
+
+
+def test_adjacent_buffers_are_not_overlap(lib):
+    """taps_bar placed right after samples_bar is legal: validation must pass it on
+    (on a machine without a GPU the call then fails in the runtime, not in validation)."""
+    B, K, M = 4, 16, 5
+    N = K * M
+    yb = 1 << 20
+    tb = yb + B * N * 8                      # immediately after samples_bar
+    rc = lib.transform_adjoint(ctypes.c_void_p(yb), ctypes.c_void_p(1 << 32),
+                               ctypes.c_void_p(1 << 34), ctypes.c_void_p(1 << 36),
+                               ctypes.c_void_p(tb), B, K, M, 0, 0, None, 0, None)
+    assert rc != nat.TF_EINVAL
+    rc = lib.transform_adjoint(ctypes.c_void_p(yb), ctypes.c_void_p(1 << 32),
+                               ctypes.c_void_p(1 << 34), ctypes.c_void_p(1 << 36),
+                               ctypes.c_void_p(tb - 8), B, K, M, 0, 0, None, 0, None)
+    assert rc == nat.TF_EINVAL

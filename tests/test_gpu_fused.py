@@ -1,0 +1,217 @@
+"""GPU parity of the fused and plain HIP paths against the FP64 oracle.
+
+Inputs are seeded; the GPU receives complex64/float32 and the oracle the same
+values upcast, so any difference is the kernels' rounding.  Bar: relative L2
+<= 1e-5 over the batch and per block (the FP32 tolerance of the benchmark spec).
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1604_06236_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1604_06236_amd import transform
+    return transform
+
+
+def _dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.complex128) if np.iscomplexobj(a) else np.asarray(a, np.float64)
+    b = np.asarray(b, np.complex128) if np.iscomplexobj(b) else np.asarray(b, np.float64)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def block_rel_l2(a, b):
+    a = np.asarray(a, np.complex128)
+    b = np.asarray(b, np.complex128)
+    return float(np.max(np.linalg.norm(a - b, axis=-1) / np.linalg.norm(b, axis=-1)))
+
+
+def _inputs(B, K, M, seed, shared=True, kind="qam16"):
+    rng = np.random.default_rng(seed)
+    N = K * M
+    if kind == "cn01":
+        S = W.cn01(rng, (B, N))
+    else:
+        S = W.qam(rng, 16, (B, N))
+    S = S.astype(np.complex64)
+    if shared:
+        taps = W.rc_taps(N, 0.3).astype(np.float32)
+    else:
+        taps = np.stack([W.rc_taps(N, a) for a in rng.uniform(0.1, 0.9, B)]).astype(np.float32)
+    return S, taps
+
+
+SHAPES = [(1, 1), (1, 7), (2, 3), (4, 16), (8, 5), (16, 5), (32, 9), (64, 3), (64, 15),
+          (128, 15), (128, 7), (256, 9), (256, 1), (512, 5), (512, 15), (1024, 3), (1024, 15),
+          (1024, 16), (16, 11), (32, 13), (8, 12), (16, 14), (64, 10), (128, 6)]
+
+
+@pytest.mark.parametrize("K,M", SHAPES)
+@pytest.mark.parametrize("compute", ["fp32", "plain_fp32"])
+def test_forward_inverse_parity(T, K, M, compute):
+    B = 37 if K * M <= 4096 else 9          # not a multiple of any blocks-per-workgroup
+    print(f"case K={K} M={M} B={B} compute={compute}", flush=True)
+    S, taps = _inputs(B, K, M, seed=K * 100 + M)
+    y_ref = O.forward(S, taps)
+    y = _host(T.transform_forward(_dev(S), _dev(taps), K, M, compute=compute))
+    assert rel_l2(y, y_ref) < TOL and block_rel_l2(y, y_ref) < TOL
+    yin = y_ref.astype(np.complex64)
+    S_ref = O.inverse(yin, taps)
+    Sg = _host(T.transform_inverse(_dev(yin), _dev(taps), K, M, compute=compute))
+    assert rel_l2(Sg, S_ref) < TOL and block_rel_l2(Sg, S_ref) < TOL
+
+
+@pytest.mark.parametrize("K,M", [(16, 5), (128, 15), (256, 9), (1024, 15), (64, 7), (2, 1)])
+@pytest.mark.parametrize("shared", [True, False])
+@pytest.mark.parametrize("compute", ["fp32", "plain_fp32"])
+def test_adjoint_and_tap_gradient(T, K, M, shared, compute):
+    B = 29 if K * M <= 4096 else 7
+    print(f"case adjoint K={K} M={M} B={B} shared={shared} compute={compute}", flush=True)
+    S, taps = _inputs(B, K, M, seed=7 + K + M, shared=shared)
+    rng = np.random.default_rng(99)
+    yb = W.cn01(rng, (B, K * M)).astype(np.complex64)
+    Sbar_ref, tb_ref = O.adjoint(yb, taps, S)
+    Sbar, tb = T.transform_adjoint(_dev(yb), _dev(taps), K, M, coeffs=_dev(S), want_taps_bar=True,
+                                   compute=compute)
+    assert rel_l2(_host(Sbar), Sbar_ref) < TOL
+    assert rel_l2(_host(tb), tb_ref) < TOL
+    # without the tap term
+    Sbar2, none = T.transform_adjoint(_dev(yb), _dev(taps), K, M, compute=compute)
+    assert none is None and rel_l2(_host(Sbar2), Sbar_ref) < TOL
+
+
+@pytest.mark.parametrize("K,M", [(16, 5), (256, 9), (128, 15)])
+@pytest.mark.parametrize("shared", [True, False])
+def test_inverse_adjoint(T, K, M, shared):
+    B = 21
+    print(f"case inverse_adjoint K={K} M={M} shared={shared}", flush=True)
+    S, taps = _inputs(B, K, M, seed=3 + K, shared=shared)
+    g = W.cn01(np.random.default_rng(5), (B, K * M)).astype(np.complex64)
+    Shat = S  # any coefficient array works for the tap term's parity
+    yb_ref, tb_ref = O.inverse_adjoint(g, taps, Shat)
+    yb, tb = T.transform_inverse_adjoint(_dev(g), _dev(taps), K, M, coeffs=_dev(Shat),
+                                         want_taps_bar=True)
+    assert rel_l2(_host(yb), yb_ref) < TOL
+    assert rel_l2(_host(tb), tb_ref) < TOL
+
+
+def test_all_schedules_agree(T):
+    """Every compiled schedule of the standard shapes meets the bar."""
+    for K, M in ((16, 5), (128, 15), (256, 9), (1024, 15)):
+        B = 19
+        S, taps = _inputs(B, K, M, seed=K)
+        y_ref = O.forward(S, taps)
+        n = len(T.schedules(K, M))
+        for idx in range(n):
+            print(f"case schedule K={K} M={M} idx={idx}", flush=True)
+            T.select_schedule(K, M, idx)
+            y = _host(T.transform_forward(_dev(S), _dev(taps), K, M))
+            assert rel_l2(y, y_ref) < TOL, (K, M, idx, T.schedules(K, M)[idx])
+            yb, tb = T.transform_adjoint(_dev(y_ref.astype(np.complex64)), _dev(taps), K, M,
+                                         coeffs=_dev(S), want_taps_bar=True)
+            sb_ref, tb_ref = O.adjoint(y_ref.astype(np.complex64), taps, S)
+            assert rel_l2(_host(yb), sb_ref) < TOL and rel_l2(_host(tb), tb_ref) < TOL
+        T.select_schedule(K, M, -1)
+
+
+def test_grid_cap_persistent_loop(T):
+    """A capped grid makes each workgroup loop over several block groups."""
+    K, M, B = 128, 15, 301
+    S, taps = _inputs(B, K, M, seed=1)
+    y_ref = O.forward(S, taps)
+    for cap in (1, 3, 64):
+        T.select_schedule(K, M, -1, grid_cap=cap)
+        y = _host(T.transform_forward(_dev(S), _dev(taps), K, M))
+        assert rel_l2(y, y_ref) < TOL
+        yb, tb = T.transform_adjoint(_dev(y_ref.astype(np.complex64)), _dev(taps), K, M,
+                                     coeffs=_dev(S), want_taps_bar=True)
+        _, tb_ref = O.adjoint(y_ref.astype(np.complex64), taps, S)
+        assert rel_l2(_host(tb), tb_ref) < TOL
+    T.select_schedule(K, M, -1, grid_cap=0)
+
+
+def test_zero_tap_sets_status(T):
+    import torch
+    K, M, B = 8, 5, 4
+    N = K * M
+    taps = W.log_series_taps(N, 0.05).astype(np.float32)   # zero at n = 0 (eq. (41))
+    y = np.ones((B, N), np.complex64)
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    S = _host(T.transform_inverse(_dev(y), _dev(taps), K, M, status=st))
+    assert int(st.item()) == 1
+    assert not np.all(np.isfinite(S[:, 0])) and np.all(np.isfinite(S[:, 1:]))
+    st.zero_()
+    T.transform_inverse(_dev(y), _dev(W.rc_taps(N, 0.5).astype(np.float32)), K, M, status=st)
+    assert int(st.item()) == 0
+
+
+def test_empty_and_errors(T):
+    import torch
+    from paper_1604_06236_amd._native import TransformError
+    K, M = 16, 5
+    z = torch.zeros((0, 80), dtype=torch.complex64, device="cuda")
+    taps = torch.ones(80, device="cuda")
+    assert T.transform_forward(z, taps, K, M).shape == (0, 80)
+    x = torch.zeros((2, 96), dtype=torch.complex64, device="cuda")
+    with pytest.raises(TransformError):
+        T.transform_forward(x, torch.ones(96, device="cuda"), 3, 32)    # K not a power of two
+    with pytest.raises(TransformError):
+        T.transform_forward(torch.zeros((1, 17 * 16), dtype=torch.complex64, device="cuda"),
+                            torch.ones(17 * 16, device="cuda"), 16, 17)
+
+
+def test_determinism(T):
+    K, M, B = 256, 9, 64
+    S, taps = _inputs(B, K, M, seed=42)
+    a = _host(T.transform_forward(_dev(S), _dev(taps), K, M))
+    b = _host(T.transform_forward(_dev(S), _dev(taps), K, M))
+    assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+    yb = _dev(a)
+    _, t1 = T.transform_adjoint(yb, _dev(taps), K, M, coeffs=_dev(S), want_taps_bar=True)
+    _, t2 = T.transform_adjoint(yb, _dev(taps), K, M, coeffs=_dev(S), want_taps_bar=True)
+    assert np.array_equal(_host(t1).view(np.uint32), _host(t2).view(np.uint32))
+
+
+@pytest.mark.parametrize("cfg", ["plain_cpu", "plain_gpu", "differentiation", "precision"])
+def test_standard_config_full_size(T, cfg):
+    """Full-size batches in the benchmark's launch configuration: a seeded sample
+    of blocks against the oracle, every block through the round trip."""
+    c = W.CONFIGS[cfg]
+    S, taps = W.make_uniform(cfg)
+    K, M = c.K, c.M
+    print(f"case full {cfg} B={S.shape[0]}", flush=True)
+    y = T.transform_forward(_dev(S), _dev(taps), K, M)
+    yh = _host(y)
+    idx = np.sort(np.random.default_rng(0).choice(S.shape[0], size=min(64, S.shape[0]), replace=False))
+    idx = np.unique(np.concatenate([idx, [0, S.shape[0] - 1]]))
+    ref = O.forward(S[idx], taps)
+    assert rel_l2(yh[idx], ref) < TOL and block_rel_l2(yh[idx], ref) < TOL
+    back = _host(T.transform_inverse(y, _dev(taps), K, M))
+    assert rel_l2(back, S) < TOL
+    sb, tb = T.transform_adjoint(y, _dev(taps), K, M, coeffs=_dev(S), want_taps_bar=True)
+    sb_ref, _ = O.adjoint(yh[idx], taps, S[idx])
+    assert rel_l2(_host(sb)[idx], sb_ref) < TOL
+    # full tap gradient: Lambdabar_n = sum_b Re(conj(S) W), with W = DFT(y) = N taps S here
+    # (since y = T S), so Lambdabar = N taps sum_b |S_n|^2 -- a property that holds at any size
+    expect = K * M * taps.astype(np.float64) * np.sum(np.abs(S.astype(np.complex128)) ** 2, axis=0)
+    assert rel_l2(_host(tb), expect) < TOL
