@@ -64,7 +64,7 @@ static std::map<std::pair<int, int>, Selection> g_select;
 struct DeviceState {
     int cus = 0;
     std::map<int, c32 *> tw;                       // entry -> twiddle table
-    std::map<int, int> occ;                        // entry -> workgroups per CU
+    std::map<std::pair<int, int>, int> occ;        // (entry, kernel variant) -> workgroups per CU
     std::map<std::pair<int, int>, c32 *> roots;    // (K, M) -> N-th roots (plain path)
 };
 static std::map<int, DeviceState> g_dev;
@@ -115,8 +115,8 @@ static int chosen_entry(int K, int M, int *grid_cap)
     return it->second[pos];
 }
 
-// per-pass twiddles: for pass p >= 1 with stride Ns and radix R, entry
-// [jm * R + r] = e^{+j 2 pi (jm r mod Ns R) / (Ns R)}, computed in double
+// base twiddles: for pass p >= 1 with stride Ns and radix R, entry [jm] =
+// e^{+j 2 pi jm / (Ns R)} for jm < Ns, computed in double and rounded once
 static std::vector<c32> build_twiddles(const FusedEntry &e)
 {
     std::vector<c32> t;
@@ -125,12 +125,10 @@ static std::vector<c32> build_twiddles(const FusedEntry &e)
     for (int p = 1; p < e.npass; ++p) {
         const long R = e.radix[p];
         const long L = ns * R;
-        for (long jm = 0; jm < ns; ++jm)
-            for (long r = 0; r < R; ++r) {
-                const long k = (jm * r) % L;
-                const double ang = 2.0 * M_PI * double(k) / double(L);
-                t.push_back(c32{float(std::cos(ang)), float(std::sin(ang))});
-            }
+        for (long jm = 0; jm < ns; ++jm) {
+            const double ang = 2.0 * M_PI * double(jm) / double(L);
+            t.push_back(c32{float(std::cos(ang)), float(std::sin(ang))});
+        }
         ns *= R;
     }
     return t;
@@ -157,8 +155,9 @@ static int upload(const std::vector<c32> &h, c32 **out)
     return TF_OK;
 }
 
-// twiddle table and occupancy of an entry on the current device (built once)
-static int entry_tables(int dev, int idx, const c32 **tw, int *occ)
+// twiddle table of an entry and occupancy of one of its kernels on the current
+// device (built once)
+static int entry_tables(int dev, int idx, int side, int tg, const c32 **tw, int *occ)
 {
     DeviceState &d = dev_state(dev);
     const FusedEntry &e = registry().entries[idx];
@@ -168,13 +167,17 @@ static int entry_tables(int dev, int idx, const c32 **tw, int *occ)
         int rc = upload(build_twiddles(e), &p);
         if (rc) return rc;
         it = d.tw.emplace(idx, p).first;
+    }
+    const int variant = side * 2 + (tg ? 1 : 0);
+    auto oc = d.occ.find({idx, variant});
+    if (oc == d.occ.end()) {
         int n = 0;
         hipError_t he = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &n, reinterpret_cast<const void *>(e.kernel), e.TB * e.BPW, 0);
-        d.occ[idx] = (he == hipSuccess && n > 0) ? n : 1;
+            &n, reinterpret_cast<const void *>(e.kernel[side][tg ? 1 : 0]), e.TB * e.BPW, 0);
+        oc = d.occ.emplace(std::make_pair(idx, variant), (he == hipSuccess && n > 0) ? n : 1).first;
     }
     *tw = it->second;
-    *occ = d.occ[idx];
+    *occ = oc->second;
     return TF_OK;
 }
 
@@ -205,14 +208,14 @@ struct Geometry {
     int64_t rows;        // partial tap-gradient rows (grid * BPW)
 };
 
-static int fused_geometry(int dev, int K, int M, int64_t nblocks, bool shared_tapgrad, Geometry *g,
-                          const c32 **tw)
+static int fused_geometry(int dev, int K, int M, int64_t nblocks, int side, bool tg,
+                          bool shared_tapgrad, Geometry *g, const c32 **tw)
 {
     int cap = 0;
     int idx = chosen_entry(K, M, &cap);
     if (idx < 0) return TF_EUNSUPPORTED;
     int occ = 1;
-    int rc = entry_tables(dev, idx, tw, &occ);
+    int rc = entry_tables(dev, idx, side, tg, tw, &occ);
     if (rc) return rc;
     const FusedEntry &e = registry().entries[idx];
     const int64_t groups = (nblocks + e.BPW - 1) / e.BPW;
@@ -292,17 +295,23 @@ extern "C" size_t transform_workspace_size(int64_t nblocks, int32_t K, int32_t M
     std::lock_guard<std::mutex> lk(g_mu);
     int dev = 0;
     if (current_device(&dev)) return 0;
-    Geometry g{};
-    const c32 *tw = nullptr;
-    if (fused_geometry(dev, K, M, nblocks, true, &g, &tw)) return 0;
-    return fused_ws_bytes(g.rows, N);
+    // large enough for either tap-gradient kernel (their occupancies may differ)
+    size_t need = 0;
+    for (int side : {int(SIDE_IN), int(SIDE_OUT)}) {
+        Geometry g{};
+        const c32 *tw = nullptr;
+        if (fused_geometry(dev, K, M, nblocks, side, true, true, &g, &tw)) return 0;
+        need = std::max(need, fused_ws_bytes(g.rows, N));
+    }
+    return need;
 }
 
-// One fused or plain run with the given element ops.
+// One fused or plain run.  side: where the filter applies (SIDE_IN: positive
+// exponent; SIDE_OUT: negative exponent); div: divide by N Lambda instead of
+// multiplying by Lambda; tg: also compute the tap gradient into taps_bar.
 static int run(const void *in, const float *taps, void *out, const void *aux, float *taps_bar,
                int32_t *status, int64_t nblocks, int32_t K, int32_t M, int64_t tap_stride,
-               int32_t compute, int conj_io, int in_op, int out_op, int tg_op, void *ws,
-               size_t ws_bytes, void *stream)
+               int32_t compute, int side, int div, bool tg, void *ws, size_t ws_bytes, void *stream)
 {
     const int64_t N = int64_t(K) * M;
     const bool shared = tap_stride == 0;
@@ -313,7 +322,8 @@ static int run(const void *in, const float *taps, void *out, const void *aux, fl
     if (rc) return rc;
 
     if (compute == TF_PLAIN_FP32) {
-        const size_t need = plain_ws_bytes(nblocks, N, tg_op != TG_NONE, shared);
+        if (tg && side == SIDE_IN) return TF_EUNSUPPORTED;
+        const size_t need = plain_ws_bytes(nblocks, N, tg, shared);
         if (!ws || ws_bytes < need || !aligned(ws, 8)) return TF_EWORKSPACE;
         const c32 *roots = nullptr;
         rc = plain_roots(dev, K, M, &roots);
@@ -331,13 +341,13 @@ static int run(const void *in, const float *taps, void *out, const void *aux, fl
         a.aux = reinterpret_cast<const c32 *>(aux);
         a.out = reinterpret_cast<c32 *>(out);
         a.status = status;
-        a.conj_io = conj_io;
-        a.in_op = in_op;
-        a.out_op = out_op;
-        a.tg_op = tg_op;
-        float *tg_rows = (tg_op != TG_NONE) ? (shared ? part : taps_bar) : nullptr;
+        a.conj_io = side == SIDE_OUT;
+        a.in_op = side == SIDE_IN ? (div ? IN_DIV_NTAP : IN_MUL_TAP) : IN_NONE;
+        a.out_op = side == SIDE_OUT ? (div ? OUT_DIV_NTAP : OUT_MUL_TAP) : OUT_NONE;
+        a.tg_op = tg ? TG_OUT : TG_NONE;
+        float *tg_rows = tg ? (shared ? part : taps_bar) : nullptr;
         hipError_t e = plain_run(a, reinterpret_cast<const c32 *>(in), ws0, ws1, tg_rows, s);
-        if (e == hipSuccess && tg_op != TG_NONE && shared)
+        if (e == hipSuccess && tg && shared)
             e = rows_reduce(part, nblocks, N, part + nblocks * N, taps_bar, s);
         if (e != hipSuccess) {
             set_error("plain launch", e);
@@ -348,10 +358,10 @@ static int run(const void *in, const float *taps, void *out, const void *aux, fl
 
     Geometry g{};
     const c32 *tw = nullptr;
-    rc = fused_geometry(dev, K, M, nblocks, tg_op != TG_NONE && shared, &g, &tw);
+    rc = fused_geometry(dev, K, M, nblocks, side, tg, tg && shared, &g, &tw);
     if (rc) return rc;
     float *part = nullptr;
-    if (tg_op != TG_NONE && shared) {
+    if (tg && shared) {
         const size_t need = fused_ws_bytes(g.rows, N);
         if (!ws || ws_bytes < need || !aligned(ws, 4)) return TF_EWORKSPACE;
         part = reinterpret_cast<float *>(ws);
@@ -362,17 +372,14 @@ static int run(const void *in, const float *taps, void *out, const void *aux, fl
     a.out = reinterpret_cast<c32 *>(out);
     a.taps = taps;
     a.aux = reinterpret_cast<const c32 *>(aux);
-    a.tapbar = (tg_op != TG_NONE) ? (shared ? part : taps_bar) : nullptr;
+    a.tapbar = tg ? (shared ? part : taps_bar) : nullptr;
     a.status = status;
     a.tw = tw;
     a.nblocks = nblocks;
     a.tap_stride = tap_stride;
-    a.conj_io = conj_io;
-    a.in_op = in_op;
-    a.out_op = out_op;
-    a.tg_op = tg_op;
-    hipError_t he = e.launch(a, g.grid, s);
-    if (he == hipSuccess && tg_op != TG_NONE && shared)
+    a.div = div;
+    hipError_t he = e.launch[side][tg ? 1 : 0](a, g.grid, s);
+    if (he == hipSuccess && tg && shared)
         he = rows_reduce(part, g.rows, N, part + g.rows * N, taps_bar, s);
     if (he != hipSuccess) {
         set_error("fused launch", he);
@@ -391,7 +398,7 @@ extern "C" int transform_forward(const void *coeffs, const float *taps, void *sa
         return split_run(0, coeffs, taps, samples, nblocks, K, M, tap_stride, compute, workspace,
                          workspace_bytes, stream);
     return run(coeffs, taps, samples, nullptr, nullptr, nullptr, nblocks, K, M, tap_stride, compute,
-               0, IN_MUL_TAP, OUT_NONE, TG_NONE, workspace, workspace_bytes, stream);
+               SIDE_IN, 0, false, workspace, workspace_bytes, stream);
 }
 
 extern "C" int transform_inverse(const void *samples, const float *taps, void *coeffs, int64_t nblocks,
@@ -404,7 +411,7 @@ extern "C" int transform_inverse(const void *samples, const float *taps, void *c
     if (status_dev && !aligned(status_dev, 4)) return TF_EINVAL;
     if (compute == TF_SPLIT_BF16 || compute == TF_SPLIT_FP16) return TF_EUNSUPPORTED;
     return run(samples, taps, coeffs, nullptr, nullptr, status_dev, nblocks, K, M, tap_stride,
-               compute, 1, IN_NONE, OUT_DIV_NTAP, TG_NONE, workspace, workspace_bytes, stream);
+               compute, SIDE_OUT, 1, false, workspace, workspace_bytes, stream);
 }
 
 extern "C" int transform_adjoint(const void *samples_bar, const float *taps, const void *coeffs,
@@ -431,8 +438,7 @@ extern "C" int transform_adjoint(const void *samples_bar, const float *taps, con
                          workspace, workspace_bytes, stream);
     }
     return run(samples_bar, taps, coeffs_bar, coeffs, taps_bar, nullptr, nblocks, K, M, tap_stride,
-               compute, 1, IN_NONE, OUT_MUL_TAP, taps_bar ? TG_OUT : TG_NONE, workspace,
-               workspace_bytes, stream);
+               compute, SIDE_OUT, 0, taps_bar != nullptr, workspace, workspace_bytes, stream);
 }
 
 extern "C" int transform_inverse_adjoint(const void *coeffs_bar, const float *taps, const void *coeffs,
@@ -449,8 +455,7 @@ extern "C" int transform_inverse_adjoint(const void *coeffs_bar, const float *ta
         if (overlap(coeffs, samples_bar, size_t(nblocks) * N * 8)) return TF_EINVAL;
     }
     return run(coeffs_bar, taps, samples_bar, coeffs, taps_bar, nullptr, nblocks, K, M, tap_stride,
-               compute, 0, IN_DIV_NTAP, OUT_NONE, taps_bar ? TG_IN : TG_NONE, workspace,
-               workspace_bytes, stream);
+               compute, SIDE_IN, 1, taps_bar != nullptr, workspace, workspace_bytes, stream);
 }
 
 extern "C" int transform_prepare(int32_t K, int32_t M, int32_t compute)
@@ -470,7 +475,7 @@ extern "C" int transform_prepare(int32_t K, int32_t M, int32_t compute)
     if (idx < 0) return TF_EUNSUPPORTED;
     const c32 *tw = nullptr;
     int occ = 0;
-    return entry_tables(dev, idx, &tw, &occ);
+    return entry_tables(dev, idx, SIDE_IN, false, &tw, &occ);
 }
 
 extern "C" const char *transform_status_string(int status)

@@ -26,26 +26,23 @@
 
 namespace bt {
 
-enum InOp : int { IN_NONE = 0, IN_MUL_TAP = 1, IN_DIV_NTAP = 2 };
-enum OutOp : int { OUT_NONE = 0, OUT_MUL_TAP = 1, OUT_DIV_NTAP = 2 };
-enum TgOp : int {
-    TG_NONE = 0,
-    TG_OUT = 1,   // Re(conj(aux_n) W_n), W taken before the output filter (forward's adjoint)
-    TG_IN = 2,    // -Re(conj(g_n) aux_n) / Lambda_n at the input (inverse's adjoint)
-};
+// Where the filter is applied.  SIDE_IN: positive exponent, filter on the
+// input (forward: multiply by Lambda; adjoint of the inverse: divide by
+// N Lambda).  SIDE_OUT: negative exponent (inputs and outputs conjugated),
+// filter on the output (adjoint: multiply; inverse: divide).
+enum Side : int { SIDE_IN = 0, SIDE_OUT = 1 };
 
 struct FusedArgs {
     const c32 *in;
     c32 *out;
     const float *taps;
-    const c32 *aux;       // S (TG_OUT) or the inverse's output (TG_IN)
+    const c32 *aux;       // S (output-side tap term) or the inverse's output (input side)
     float *tapbar;        // per block [B][N] when tap_stride != 0, else partial rows [grid*BPW][N]
-    int *status;          // set to 1 when a zero tap is met by IN/OUT_DIV_NTAP (nullable)
-    const c32 *tw;        // per-pass twiddle table of the plan
+    int *status;          // set to 1 when a divide meets a zero tap (nullable)
+    const c32 *tw;        // base twiddles of the plan
     int64_t nblocks;
     int64_t tap_stride;   // 0: one tap vector for all blocks; N: one per block
-    int conj_io;
-    int in_op, out_op, tg_op;
+    int div;              // 0: multiply by Lambda_n; 1: divide by N Lambda_n
 };
 
 template <int... Rs>
@@ -68,11 +65,11 @@ struct Radices {
         for (int q = 0; q < i; ++q) p *= get(q);
         return p;
     }
-    // twiddle-table offset of pass i (passes >= 1 own Ns*R entries each)
+    // offset of pass i's base roots in the twiddle table (passes >= 1 own Ns entries each)
     static constexpr int tw_off(int i)
     {
         int o = 0;
-        for (int q = 1; q < i; ++q) o += ns(q) * get(q);
+        for (int q = 1; q < i; ++q) o += ns(q);
         return o;
     }
     static constexpr int tw_total() { return tw_off(count); }
@@ -99,45 +96,100 @@ struct PrependM<1, Radices<>> {
     using type = Radices<1>;
 };
 
+// ------------------------------------------------------------------ helpers
+// Workgroup barrier that orders LDS only: global loads issued before it stay in
+// flight (a full __syncthreads would wait for them).
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// v_r *= w1^r for r = 1..R-1; the powers come from one base root by squaring
+// and single multiplications (at most 2 log2 R products deep)
+template <int R>
+__device__ __forceinline__ void apply_twiddles(c32 (&v)[R], c32 w1)
+{
+    if constexpr (R > 1) {
+        c32 w[R];
+        w[1] = w1;
+        static_for<2, R>([&](auto rI) {
+            constexpr int r = decltype(rI)::value;
+            if constexpr (r % 2 == 0) {
+                const c32 h = w[r / 2];
+                w[r] = c32{h.x * h.x - h.y * h.y, 2.0f * h.x * h.y};
+            } else {
+                w[r] = cmul(w[r - 1], w1);
+            }
+        });
+        static_for<1, R>([&](auto rI) {
+            constexpr int r = decltype(rI)::value;
+            v[r] = cmul(v[r], w[r]);
+        });
+    }
+}
+
+// register slots of the base twiddles held by one thread: pass p >= 1 owns
+// IT_p consecutive slots
+template <class PL, int TB>
+struct TwSlots {
+    static constexpr int it(int p) { return (PL::total() / PL::get(p) + TB - 1) / TB; }
+    static constexpr int off(int p)
+    {
+        int o = 0;
+        for (int q = 1; q < p; ++q) o += it(q);
+        return o;
+    }
+    static constexpr int total() { return PL::count > 1 ? off(PL::count) : 1; }
+};
+
+// ------------------------------------------------------------------ buffer I/O
+// HBM traffic goes through raw buffer instructions on a resource that covers
+// exactly the valid blocks of the current group: the per-radix offsets become
+// scalar offsets (one address VGPR per thread), and accesses past the valid
+// range read 0 / are dropped by the hardware range check.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, kRsrcWord3);
+}
+
+__device__ __forceinline__ c32 ld_c(rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(c32, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
+__device__ __forceinline__ float ld_f(rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void st_c(c32 v, rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+}
+
+__device__ __forceinline__ void st_f(float v, rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, soff, 0);
+}
+
 // ------------------------------------------------------------------ element ops
-BT_HD c32 load_c(const c32 *p) { return *p; }
-
-__device__ __forceinline__ c32 in_transform(const FusedArgs &a, c32 x, const float *tp, int64_t n,
-                                             float Nf, const c32 *auxb, float *tg)
+// filter factor: Lambda_n, or 1/(N Lambda_n) (v_rcp, 1 ulp; Inf for a zero tap)
+__device__ __forceinline__ float filter_factor(float t, int div, float Nf)
 {
-    if (a.in_op == IN_DIV_NTAP && a.tg_op == TG_IN) {
-        // -Re(conj(g_n) Shat_n) / Lambda_n, from the unconjugated input
-        *tg = -(x.x * auxb[n].x + x.y * auxb[n].y) / tp[n];
-    }
-    if (a.conj_io) x = conj(x);
-    if (a.in_op == IN_MUL_TAP) {
-        x = scale(x, tp[n]);
-    } else if (a.in_op == IN_DIV_NTAP) {
-        const float t = tp[n];
-        if (t == 0.0f && a.status) *a.status = 1;
-        x = scale(x, 1.0f / (Nf * t));
-    }
-    return x;
+    const float r = __builtin_amdgcn_rcpf(Nf * t);
+    return div ? r : t;
 }
 
-__device__ __forceinline__ c32 out_transform(const FusedArgs &a, c32 w, const float *tp, int64_t k,
-                                              float Nf, const c32 *auxb, float *tg)
-{
-    if (a.conj_io) w = conj(w);
-    if (a.tg_op == TG_OUT) *tg = auxb[k].x * w.x + auxb[k].y * w.y;
-    if (a.out_op == OUT_MUL_TAP) {
-        w = scale(w, tp[k]);
-    } else if (a.out_op == OUT_DIV_NTAP) {
-        const float t = tp[k];
-        if (t == 0.0f && a.status) *a.status = 1;
-        w = scale(w, 1.0f / (Nf * t));
-    }
-    return w;
-}
-
-// ------------------------------------------------------------------ passes
+// ------------------------------------------------------------------ LDS passes
 template <class PL, int TB, int P>
-__device__ __forceinline__ void lds_passes(c32 *L, int tid, const c32 *tw)
+__device__ __forceinline__ void lds_passes(c32 *L, int tid, const c32 *w1s)
 {
     if constexpr (P < PL::count - 1) {
         constexpr int N = PL::total();
@@ -145,40 +197,44 @@ __device__ __forceinline__ void lds_passes(c32 *L, int tid, const c32 *tw)
         constexpr int NS = PL::ns(P);
         constexpr int NB = N / R;
         constexpr int IT = (NB + TB - 1) / TB;
-        constexpr int TWO = PL::tw_off(P);
+        constexpr int SLOT = TwSlots<PL, TB>::off(P);
         c32 v[IT][R];
 #pragma unroll
         for (int i = 0; i < IT; ++i) {
             const int j = tid + i * TB;
             if (IT * TB == NB || j < NB) {
-#pragma unroll
-                for (int r = 0; r < R; ++r) v[i][r] = L[j + r * NB];
-                const int jm = j % NS;
-                const c32 *t = tw + TWO + jm * R;
-#pragma unroll
-                for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], t[r]);
+                static_for<0, R>([&](auto rI) {
+                    constexpr int r = decltype(rI)::value;
+                    v[i][r] = L[j + r * NB];
+                });
+                apply_twiddles<R>(v[i], w1s[SLOT + i]);
                 dft<R>(v[i]);
             }
         }
-        __syncthreads();
+        lds_barrier();
 #pragma unroll
         for (int i = 0; i < IT; ++i) {
             const int j = tid + i * TB;
             if (IT * TB == NB || j < NB) {
                 const int jm = j % NS;
                 const int base = (j / NS) * NS * R + jm;
-#pragma unroll
-                for (int r = 0; r < R; ++r) L[base + r * NS] = v[i][r];
+                static_for<0, R>([&](auto rI) {
+                    constexpr int r = decltype(rI)::value;
+                    L[base + r * NS] = v[i][r];
+                });
             }
         }
-        __syncthreads();
-        lds_passes<PL, TB, P + 1>(L, tid, tw);
+        lds_barrier();
+        lds_passes<PL, TB, P + 1>(L, tid, w1s);
     }
 }
 
-template <class PL, int TB, int BPW>
+// SIDE: where the filter applies (and the exponent sign); TGR: with the tap gradient
+template <class PL, int TB, int BPW, int SIDE, bool TGR>
 __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
 {
+    constexpr int TG = !TGR ? 0 : (SIDE == SIDE_OUT ? 1 : 2);
+    constexpr int TG_OUT_ = 1, TG_IN_ = 2;
     constexpr int N = PL::total();
     constexpr int NP = PL::count;
     constexpr int R0 = PL::get(0);
@@ -188,9 +244,12 @@ __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
     constexpr int NSL = PL::ns(NP - 1);
     constexpr int NBL = N / RL;
     constexpr int ITL = (NBL + TB - 1) / TB;
-    constexpr int TWL = PL::tw_off(NP - 1);
-    // tap-gradient accumulators live on the side of the pass that computes them
-    constexpr int TGI = (IT0 * R0 > ITL * RL) ? IT0 * R0 : ITL * RL;
+    constexpr bool FULL0 = IT0 * TB == NB0;
+    constexpr bool FULLL = ITL * TB == NBL;
+    constexpr int NACC = TG == TG_OUT_ ? ITL * RL : (TG == TG_IN_ ? IT0 * R0 : 1);
+    constexpr bool CONJ = SIDE == SIDE_OUT;
+    constexpr uint32_t CB = 8;      // bytes per complex
+    constexpr uint32_t FB = 4;      // bytes per tap
 
     __shared__ c32 lds[NP > 1 ? BPW * N : 1];
     const int bi = threadIdx.x / TB;
@@ -198,128 +257,229 @@ __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
     c32 *L = lds + (NP > 1 ? bi * N : 0);
     const float Nf = float(N);
     const bool shared_taps = (a.tap_stride == 0);
+    const int64_t ngroups = (a.nblocks + BPW - 1) / BPW;
+    // element offset of this thread's block inside its group
+    const uint32_t boff = uint32_t(bi) * N;
 
-    float acc[TGI];
+    bool zero_tap = false;
+    float acc[NACC];
 #pragma unroll
-    for (int q = 0; q < TGI; ++q) acc[q] = 0.0f;
+    for (int q = 0; q < NACC; ++q) acc[q] = 0.0f;
 
-    for (int64_t g = blockIdx.x; g * BPW < a.nblocks; g += gridDim.x) {
-        const int64_t blk = g * BPW + bi;
-        const bool valid = blk < a.nblocks;
-        const c32 *inb = a.in + blk * N;
-        c32 *outb = a.out + blk * N;
-        const float *tp = a.taps + blk * a.tap_stride;
-        const c32 *auxb = a.aux ? a.aux + blk * N : nullptr;
-        float *tgb = a.tapbar + (shared_taps ? 0 : blk * N);
+    // base twiddles of every pass >= 1, held for the whole kernel
+    c32 w1s[TwSlots<PL, TB>::total()];
+    if constexpr (NP > 1) {
+        static_for<1, NP>([&](auto pI) {
+            constexpr int P = decltype(pI)::value;
+            constexpr int NB = N / PL::get(P);
+            constexpr int IT = TwSlots<PL, TB>::it(P);
+#pragma unroll
+            for (int i = 0; i < IT; ++i) {
+                const int j = tid + i * TB;
+                w1s[TwSlots<PL, TB>::off(P) + i] =
+                    (j < NB) ? a.tw[PL::tw_off(P) + j % PL::ns(P)] : c32{1.f, 0.f};
+            }
+        });
+    }
+
+    // resources over the valid blocks of group g
+    auto group_blocks = [&](int64_t g) -> uint32_t {
+        const int64_t left = a.nblocks - g * BPW;
+        return uint32_t(left < BPW ? left : BPW);
+    };
+    auto rs_cplx = [&](const c32 *base, int64_t g) {
+        return make_rsrc(base + g * BPW * N, group_blocks(g) * N * CB);
+    };
+    auto rs_taps = [&](int64_t g) {
+        return shared_taps ? make_rsrc(a.taps, N * FB)
+                           : make_rsrc(a.taps + g * BPW * N, group_blocks(g) * N * FB);
+    };
+
+    // pass-0 operands of the group being processed: raw input and input-side taps
+    c32 x0[IT0][R0];
+    float t0[SIDE == SIDE_IN ? IT0 : 1][SIDE == SIDE_IN ? R0 : 1];
+    auto fetch = [&](int64_t g) {
+        const rsrc_t ri = rs_cplx(a.in, g);
+        const rsrc_t rt = rs_taps(g);
+        const uint32_t tb = shared_taps ? 0u : boff;
+#pragma unroll
+        for (int i = 0; i < IT0; ++i) {
+            const int j = tid + i * TB;
+            if (FULL0 || j < NB0) {
+                static_for<0, R0>([&](auto rI) {
+                    constexpr int r = decltype(rI)::value;
+                    x0[i][r] = ld_c(ri, (boff + j) * CB, r * NB0 * CB);
+                    if constexpr (SIDE == SIDE_IN) t0[i][r] = ld_f(rt, (tb + j) * FB, r * NB0 * FB);
+                });
+            }
+        }
+    };
+
+    int64_t g = blockIdx.x;
+    if (g < ngroups) fetch(g);
+    for (; g < ngroups; g += gridDim.x) {
+        const rsrc_t ro = rs_cplx(a.out, g);
+        const rsrc_t rt = rs_taps(g);
+        const uint32_t tb = shared_taps ? 0u : boff;
+        rsrc_t rx = ro, rg = ro;
+        if constexpr (TG != 0) {
+            rx = rs_cplx(a.aux, g);
+            rg = shared_taps ? ro : make_rsrc(a.tapbar + g * BPW * N, group_blocks(g) * N * FB);
+        }
 
         if constexpr (NP == 1) {
-            // the whole transform is one radix-N butterfly per block
 #pragma unroll
             for (int i = 0; i < IT0; ++i) {
                 const int j = tid + i * TB;
-                if (valid && (IT0 * TB == NB0 || j < NB0)) {
+                if (FULL0 || j < NB0) {
                     c32 v[R0];
-#pragma unroll
-                    for (int r = 0; r < R0; ++r) {
-                        float tg = 0.f;
-                        v[r] = in_transform(a, inb[j + r * NB0], tp, j + r * NB0, Nf, auxb, &tg);
-                        if (a.tg_op == TG_IN) {
+                    static_for<0, R0>([&](auto rI) {
+                        constexpr int r = decltype(rI)::value;
+                        if constexpr (TG == TG_IN_) {
+                            const c32 s = ld_c(rx, (boff + j) * CB, r * NB0 * CB);
+                            const float tg = -(x0[i][r].x * s.x + x0[i][r].y * s.y) / t0[i][r];
                             if (shared_taps) acc[i * R0 + r] += tg;
-                            else tgb[j + r * NB0] = tg;
+                            else st_f(tg, rg, (boff + j) * FB, r * NB0 * FB);
                         }
-                    }
+                        if constexpr (SIDE == SIDE_IN) {
+                            zero_tap |= (t0[i][r] == 0.0f);
+                            v[r] = scale(x0[i][r], filter_factor(t0[i][r], a.div, Nf));
+                        } else {
+                            v[r] = conj(x0[i][r]);
+                        }
+                    });
                     dft<R0>(v);
-#pragma unroll
-                    for (int r = 0; r < R0; ++r) {
-                        const int k = j + r * NB0;
-                        float tg = 0.f;
-                        outb[k] = out_transform(a, v[r], tp, k, Nf, auxb, &tg);
-                        if (a.tg_op == TG_OUT) {
+                    static_for<0, R0>([&](auto rI) {
+                        constexpr int r = decltype(rI)::value;
+                        c32 w = CONJ ? conj(v[r]) : v[r];
+                        if constexpr (TG == TG_OUT_) {
+                            const c32 s = ld_c(rx, (boff + j) * CB, r * NB0 * CB);
+                            const float tg = s.x * w.x + s.y * w.y;
                             if (shared_taps) acc[i * R0 + r] += tg;
-                            else tgb[k] = tg;
+                            else st_f(tg, rg, (boff + j) * FB, r * NB0 * FB);
                         }
-                    }
+                        if constexpr (SIDE == SIDE_OUT) {
+                            const float t = ld_f(rt, (tb + j) * FB, r * NB0 * FB);
+                            zero_tap |= (t == 0.0f);
+                            w = scale(w, filter_factor(t, a.div, Nf));
+                        }
+                        st_c(w, ro, (boff + j) * CB, r * NB0 * CB);
+                    });
                 }
             }
+            if (g + gridDim.x < ngroups) fetch(g + gridDim.x);
         } else {
-            // ---- pass 0: HBM -> registers -> DFT_R0 -> LDS (no twiddle, Ns = 1)
+            // ---- pass 0 on the fetched operands: filter, length-R0 DFT (no twiddle, Ns = 1)
             c32 v0[IT0][R0];
 #pragma unroll
             for (int i = 0; i < IT0; ++i) {
                 const int j = tid + i * TB;
-                if (valid && (IT0 * TB == NB0 || j < NB0)) {
-#pragma unroll
-                    for (int r = 0; r < R0; ++r) {
-                        float tg = 0.f;
-                        v0[i][r] = in_transform(a, inb[j + r * NB0], tp, j + r * NB0, Nf, auxb, &tg);
-                        if (a.tg_op == TG_IN) {
+                if (FULL0 || j < NB0) {
+                    static_for<0, R0>([&](auto rI) {
+                        constexpr int r = decltype(rI)::value;
+                        if constexpr (TG == TG_IN_) {
+                            const c32 s = ld_c(rx, (boff + j) * CB, r * NB0 * CB);
+                            const float tg = -(x0[i][r].x * s.x + x0[i][r].y * s.y) / t0[i][r];
                             if (shared_taps) acc[i * R0 + r] += tg;
-                            else tgb[j + r * NB0] = tg;
+                            else st_f(tg, rg, (boff + j) * FB, r * NB0 * FB);
                         }
-                    }
+                        if constexpr (SIDE == SIDE_IN) {
+                            zero_tap |= (t0[i][r] == 0.0f);
+                            v0[i][r] = scale(x0[i][r], filter_factor(t0[i][r], a.div, Nf));
+                        } else {
+                            v0[i][r] = conj(x0[i][r]);
+                        }
+                    });
                     dft<R0>(v0[i]);
                 }
             }
-            __syncthreads();   // the previous group's last pass has finished reading LDS
+            lds_barrier();   // the previous group's last pass has finished reading LDS
 #pragma unroll
             for (int i = 0; i < IT0; ++i) {
                 const int j = tid + i * TB;
-                if (valid && (IT0 * TB == NB0 || j < NB0)) {
-#pragma unroll
-                    for (int r = 0; r < R0; ++r) L[j * R0 + r] = v0[i][r];
+                if (FULL0 || j < NB0) {
+                    static_for<0, R0>([&](auto rI) {
+                        constexpr int r = decltype(rI)::value;
+                        L[j * R0 + r] = v0[i][r];
+                    });
                 }
             }
-            __syncthreads();
-
-            // ---- middle passes in LDS
-            lds_passes<PL, TB, 1>(L, tid, a.tw);
-
-            // ---- last pass: LDS -> registers -> twiddle -> DFT_RL -> HBM
+            // ---- start reading the next group while this one runs in LDS, and the
+            //      operands the last pass needs (output-side taps, S for the tap term)
+            if (g + gridDim.x < ngroups) fetch(g + gridDim.x);
+            float tl[SIDE == SIDE_OUT ? ITL : 1][SIDE == SIDE_OUT ? RL : 1];
+            c32 sl[TG == TG_OUT_ ? ITL : 1][TG == TG_OUT_ ? RL : 1];
 #pragma unroll
             for (int i = 0; i < ITL; ++i) {
                 const int j = tid + i * TB;
-                if (valid && (ITL * TB == NBL || j < NBL)) {
+                if (FULLL || j < NBL) {
+                    static_for<0, RL>([&](auto rI) {
+                        constexpr int r = decltype(rI)::value;
+                        if constexpr (SIDE == SIDE_OUT) tl[i][r] = ld_f(rt, (tb + j) * FB, r * NSL * FB);
+                        if constexpr (TG == TG_OUT_) sl[i][r] = ld_c(rx, (boff + j) * CB, r * NSL * CB);
+                    });
+                }
+            }
+            lds_barrier();
+
+            // ---- middle passes in LDS
+            lds_passes<PL, TB, 1>(L, tid, w1s);
+
+            // ---- last pass: LDS -> registers -> twiddle -> DFT_RL -> HBM
+            constexpr int SLOTL = TwSlots<PL, TB>::off(NP - 1);
+#pragma unroll
+            for (int i = 0; i < ITL; ++i) {
+                const int j = tid + i * TB;
+                if (FULLL || j < NBL) {
                     c32 v[RL];
-#pragma unroll
-                    for (int r = 0; r < RL; ++r) v[r] = L[j + r * NBL];
-                    const c32 *t = a.tw + TWL + j * RL;    // j < NBL = NSL, so j mod NSL = j
-#pragma unroll
-                    for (int r = 1; r < RL; ++r) v[r] = cmul(v[r], t[r]);
+                    static_for<0, RL>([&](auto rI) {
+                        constexpr int r = decltype(rI)::value;
+                        v[r] = L[j + r * NBL];
+                    });
+                    apply_twiddles<RL>(v, w1s[SLOTL + i]);
                     dft<RL>(v);
-#pragma unroll
-                    for (int r = 0; r < RL; ++r) {
-                        const int k = j + r * NSL;
-                        float tg = 0.f;
-                        outb[k] = out_transform(a, v[r], tp, k, Nf, auxb, &tg);
-                        if (a.tg_op == TG_OUT) {
+                    static_for<0, RL>([&](auto rI) {
+                        constexpr int r = decltype(rI)::value;
+                        c32 w = CONJ ? conj(v[r]) : v[r];
+                        if constexpr (TG == TG_OUT_) {
+                            const float tg = sl[i][r].x * w.x + sl[i][r].y * w.y;
                             if (shared_taps) acc[i * RL + r] += tg;
-                            else tgb[k] = tg;
+                            else st_f(tg, rg, (boff + j) * FB, r * NSL * FB);
                         }
-                    }
+                        if constexpr (SIDE == SIDE_OUT) {
+                            zero_tap |= (tl[i][r] == 0.0f);
+                            w = scale(w, filter_factor(tl[i][r], a.div, Nf));
+                        }
+                        st_c(w, ro, (boff + j) * CB, r * NSL * CB);
+                    });
                 }
             }
         }
     }
 
+    if (zero_tap && a.div && a.status) *a.status = 1;
+
     // ---- shared taps: one partial row of the tap gradient per (workgroup, block slot)
-    if (a.tg_op != TG_NONE && shared_taps) {
-        float *row = a.tapbar + (int64_t(blockIdx.x) * BPW + bi) * N;
-        if (a.tg_op == TG_IN || NP == 1) {
+    if constexpr (TG != 0) {
+        if (shared_taps) {
+            float *row = a.tapbar + (int64_t(blockIdx.x) * BPW + bi) * N;
+            if constexpr (TG == TG_IN_ || NP == 1) {
 #pragma unroll
-            for (int i = 0; i < IT0; ++i) {
-                const int j = tid + i * TB;
-                if (IT0 * TB == NB0 || j < NB0) {
+                for (int i = 0; i < IT0; ++i) {
+                    const int j = tid + i * TB;
+                    if (FULL0 || j < NB0) {
 #pragma unroll
-                    for (int r = 0; r < R0; ++r) row[j + r * NB0] = acc[i * R0 + r];
+                        for (int r = 0; r < R0; ++r) row[j + r * NB0] = acc[i * R0 + r];
+                    }
                 }
-            }
-        } else {
+            } else {
 #pragma unroll
-            for (int i = 0; i < ITL; ++i) {
-                const int j = tid + i * TB;
-                if (ITL * TB == NBL || j < NBL) {
+                for (int i = 0; i < ITL; ++i) {
+                    const int j = tid + i * TB;
+                    if (FULLL || j < NBL) {
 #pragma unroll
-                    for (int r = 0; r < RL; ++r) row[j + r * NSL] = acc[i * RL + r];
+                        for (int r = 0; r < RL; ++r) row[j + r * NSL] = acc[i * RL + r];
+                    }
                 }
             }
         }
@@ -337,20 +497,22 @@ struct FusedEntry {
     int radix[8];
     int tw_entries;
     int lds_bytes;
-    fused_launch_fn launch;
-    const void *kernel;   // for occupancy queries
+    fused_launch_fn launch[2][2];     // [side][with tap gradient]
+    const void *kernel[2][2];         // for occupancy queries
 };
 
-template <class PL, int TB, int BPW>
+template <class PL, int TB, int BPW, int SIDE, bool TGR>
 hipError_t fused_launch(const FusedArgs &a, unsigned grid, hipStream_t s)
 {
-    hipLaunchKernelGGL((fused_kernel<PL, TB, BPW>), dim3(grid), dim3(TB * BPW), 0, s, a);
+    hipLaunchKernelGGL((fused_kernel<PL, TB, BPW, SIDE, TGR>), dim3(grid), dim3(TB * BPW), 0, s, a);
     return hipGetLastError();
 }
 
 template <class PL, int TB, int BPW>
 FusedEntry make_entry(int K, int M)
 {
+    static_assert(PL::total() <= 16384, "block too large");
+    static_assert(PL::count <= 8, "too many passes");
     FusedEntry e{};
     e.K = K;
     e.M = M;
@@ -360,8 +522,14 @@ FusedEntry make_entry(int K, int M)
     for (int i = 0; i < PL::count && i < 8; ++i) e.radix[i] = PL::get(i);
     e.tw_entries = PL::tw_total();
     e.lds_bytes = PL::count > 1 ? BPW * PL::total() * (int)sizeof(c32) : 0;
-    e.launch = &fused_launch<PL, TB, BPW>;
-    e.kernel = reinterpret_cast<const void *>(&fused_kernel<PL, TB, BPW>);
+    e.launch[0][0] = &fused_launch<PL, TB, BPW, SIDE_IN, false>;
+    e.launch[0][1] = &fused_launch<PL, TB, BPW, SIDE_IN, true>;
+    e.launch[1][0] = &fused_launch<PL, TB, BPW, SIDE_OUT, false>;
+    e.launch[1][1] = &fused_launch<PL, TB, BPW, SIDE_OUT, true>;
+    e.kernel[0][0] = reinterpret_cast<const void *>(&fused_kernel<PL, TB, BPW, SIDE_IN, false>);
+    e.kernel[0][1] = reinterpret_cast<const void *>(&fused_kernel<PL, TB, BPW, SIDE_IN, true>);
+    e.kernel[1][0] = reinterpret_cast<const void *>(&fused_kernel<PL, TB, BPW, SIDE_OUT, false>);
+    e.kernel[1][1] = reinterpret_cast<const void *>(&fused_kernel<PL, TB, BPW, SIDE_OUT, true>);
     return e;
 }
 

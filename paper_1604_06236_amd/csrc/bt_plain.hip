@@ -13,7 +13,6 @@
 #include <stdint.h>
 
 #include "bt_dft.hpp"
-#include "bt_fused.hpp"
 #include "bt_plain.hpp"
 
 namespace bt {

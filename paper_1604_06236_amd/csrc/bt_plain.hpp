@@ -8,6 +8,10 @@
 
 namespace bt {
 
+enum PlainInOp : int { IN_NONE = 0, IN_MUL_TAP = 1, IN_DIV_NTAP = 2 };
+enum PlainOutOp : int { OUT_NONE = 0, OUT_MUL_TAP = 1, OUT_DIV_NTAP = 2 };
+enum PlainTgOp : int { TG_NONE = 0, TG_OUT = 1 };
+
 struct PlainArgs {
     int K, M;
     int64_t nblocks;
