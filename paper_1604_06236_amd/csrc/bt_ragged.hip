@@ -1,16 +1,539 @@
-// Ragged batches (placeholder until the persistent kernel lands).
+// Ragged batches: blocks of different (K, M) in one persistent launch.
+//
+// Every block is an independent instance of the transform of eq. (6) on its
+// own grid (its own N = K M, filter and offset).  The plan groups blocks of
+// one (K, M) class into tiles (as many blocks as fill a workgroup), sorts the
+// tiles by cost (N log2 N per block, largest first) and lays them out as work
+// items.  One persistent kernel, sized to the resident capacity of the GPU,
+// drains the items through an atomic counter; each item runs the class's
+// compiled tile body (radix plan, threads per block, blocks per tile) with
+// the same pass machinery as the uniform kernel.  The counter is cleared by a
+// one-thread kernel launched just before, so the pair can be captured in a
+// HIP graph and replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
 #include "../../include/blocktransform.h"
 #include "bt_api_internal.hpp"
+#include "bt_fused.hpp"
 
-extern "C" int transform_ragged_plan_create(const int32_t *, const int32_t *, const int64_t *,
-                                            const int64_t *, int64_t, int64_t, tf_ragged_plan *plan)
+namespace bt {
+
+constexpr int RT = 1024;  // threads per workgroup of the persistent kernel
+
+struct RaggedItem {
+    int cls;              // class index
+    int first;            // first entry in the block order
+    int count;            // blocks in this tile (<= BPW of the class)
+    int pad;
+};
+
+struct RaggedArgs {
+    const c32 *in;
+    c32 *out;
+    const float *taps;
+    const c32 *aux;
+    float *tapbar;
+    int *status;
+    const int64_t *x_off;     // per block (original numbering)
+    const int64_t *tap_off;
+    const int *order;         // blocks sorted by class and cost
+    const RaggedItem *items;
+    const c32 *tw;            // concatenated base-root tables of the classes
+    const int *tw_off;        // per class
+    int *counter;
+    int nitems;
+    int div;
+};
+
+// tile body of one class: up to BPW blocks, TB threads each (TB >= 64, so a
+// wave never straddles two blocks and block bases are wave-uniform)
+template <class PL, int TB, int BPW, int SIDE, bool TGR>
+__device__ __forceinline__ void ragged_tile(const RaggedArgs &a, const RaggedItem &it, c32 *lds)
 {
-    if (plan) *plan = nullptr;
-    return TF_EUNSUPPORTED;
+    static_assert(TB * BPW == RT, "tile must fill the workgroup");
+    static_assert(TB >= 64, "a wave must stay inside one block");
+    constexpr int N = PL::total();
+    constexpr int NP = PL::count;
+    constexpr int R0 = PL::get(0);
+    constexpr int NB0 = N / R0;
+    constexpr int IT0 = (NB0 + TB - 1) / TB;
+    constexpr int RL = PL::get(NP - 1);
+    constexpr int NSL = PL::ns(NP - 1);
+    constexpr int NBL = N / RL;
+    constexpr int ITL = (NBL + TB - 1) / TB;
+    constexpr bool FULL0 = IT0 * TB == NB0;
+    constexpr bool FULLL = ITL * TB == NBL;
+    constexpr uint32_t CB = 8, FB = 4;
+    constexpr bool CONJ = SIDE == SIDE_OUT;
+    const float Nf = float(N);
+
+    const int bi = threadIdx.x / TB;
+    const int tid = threadIdx.x - bi * TB;
+    c32 *L = lds + bi * N;
+    const bool valid = bi < it.count;
+    // wave-uniform block offsets
+    int blk = valid ? a.order[it.first + bi] : 0;
+    blk = __builtin_amdgcn_readfirstlane(blk);
+    const int64_t xo = a.x_off[blk];
+    const int64_t to = a.tap_off[blk];
+    const uint32_t nb = valid ? N : 0;          // empty resources for idle slots
+    const rsrc_t ri = make_rsrc(a.in + xo, nb * CB);
+    const rsrc_t ro = make_rsrc(a.out + xo, nb * CB);
+    const rsrc_t rt = make_rsrc(a.taps + to, nb * FB);
+    rsrc_t rx = ro, rg = ro;
+    if constexpr (TGR) {
+        rx = make_rsrc(a.aux + xo, nb * CB);
+        rg = make_rsrc(a.tapbar + xo, nb * FB);
+    }
+    bool zero_tap = false;
+
+    c32 w1s[TwSlots<PL, TB>::total()];
+    if constexpr (NP > 1) {
+        const c32 *tw = a.tw + a.tw_off[it.cls];
+        static_for<1, NP>([&](auto pI) {
+            constexpr int P = decltype(pI)::value;
+            constexpr int NB = N / PL::get(P);
+            constexpr int IT = TwSlots<PL, TB>::it(P);
+#pragma unroll
+            for (int i = 0; i < IT; ++i) {
+                const int j = tid + i * TB;
+                w1s[TwSlots<PL, TB>::off(P) + i] = (j < NB) ? tw[PL::tw_off(P) + j % PL::ns(P)] : c32{1.f, 0.f};
+            }
+        });
+    }
+
+    // ---- pass 0: HBM -> registers -> filter -> DFT_R0
+    c32 v0[IT0][R0];
+#pragma unroll
+    for (int i = 0; i < IT0; ++i) {
+        const int j = tid + i * TB;
+        if (FULL0 || j < NB0) {
+            static_for<0, R0>([&](auto rI) {
+                constexpr int r = decltype(rI)::value;
+                c32 x = ld_c(ri, j * CB, r * NB0 * CB);
+                if constexpr (SIDE == SIDE_IN) {
+                    const float t = ld_f(rt, j * FB, r * NB0 * FB);
+                    zero_tap |= valid && (t == 0.0f);
+                    x = scale(x, filter_factor(t, a.div, Nf));
+                } else {
+                    x = conj(x);
+                }
+                v0[i][r] = x;
+            });
+            dft<R0>(v0[i]);
+        }
+    }
+    if constexpr (NP == 1) {
+#pragma unroll
+        for (int i = 0; i < IT0; ++i) {
+            const int j = tid + i * TB;
+            if (FULL0 || j < NB0) {
+                static_for<0, R0>([&](auto rI) {
+                    constexpr int r = decltype(rI)::value;
+                    c32 w = CONJ ? conj(v0[i][r]) : v0[i][r];
+                    if constexpr (TGR) {
+                        const c32 s = ld_c(rx, j * CB, r * NB0 * CB);
+                        st_f(s.x * w.x + s.y * w.y, rg, j * FB, r * NB0 * FB);
+                    }
+                    if constexpr (SIDE == SIDE_OUT) {
+                        const float t = ld_f(rt, j * FB, r * NB0 * FB);
+                        zero_tap |= valid && (t == 0.0f);
+                        w = scale(w, filter_factor(t, a.div, Nf));
+                    }
+                    st_c(w, ro, j * CB, r * NB0 * CB);
+                });
+            }
+        }
+    } else {
+        lds_barrier();   // the previous item's last pass has finished reading LDS
+#pragma unroll
+        for (int i = 0; i < IT0; ++i) {
+            const int j = tid + i * TB;
+            if (FULL0 || j < NB0) {
+                static_for<0, R0>([&](auto rI) {
+                    constexpr int r = decltype(rI)::value;
+                    L[j * R0 + r] = v0[i][r];
+                });
+            }
+        }
+        // operands of the last pass, fetched while the LDS passes run
+        float tl[SIDE == SIDE_OUT ? ITL : 1][SIDE == SIDE_OUT ? RL : 1];
+        c32 sl[TGR ? ITL : 1][TGR ? RL : 1];
+#pragma unroll
+        for (int i = 0; i < ITL; ++i) {
+            const int j = tid + i * TB;
+            if (FULLL || j < NBL) {
+                static_for<0, RL>([&](auto rI) {
+                    constexpr int r = decltype(rI)::value;
+                    if constexpr (SIDE == SIDE_OUT) tl[i][r] = ld_f(rt, j * FB, r * NSL * FB);
+                    if constexpr (TGR) sl[i][r] = ld_c(rx, j * CB, r * NSL * CB);
+                });
+            }
+        }
+        lds_barrier();
+        lds_passes<PL, TB, 1>(L, tid, w1s);
+        constexpr int SLOTL = TwSlots<PL, TB>::off(NP - 1);
+#pragma unroll
+        for (int i = 0; i < ITL; ++i) {
+            const int j = tid + i * TB;
+            if (FULLL || j < NBL) {
+                c32 v[RL];
+                static_for<0, RL>([&](auto rI) {
+                    constexpr int r = decltype(rI)::value;
+                    v[r] = L[j + r * NBL];
+                });
+                apply_twiddles<RL>(v, w1s[SLOTL + i]);
+                dft<RL>(v);
+                static_for<0, RL>([&](auto rI) {
+                    constexpr int r = decltype(rI)::value;
+                    c32 w = CONJ ? conj(v[r]) : v[r];
+                    if constexpr (TGR) st_f(sl[i][r].x * w.x + sl[i][r].y * w.y, rg, j * FB, r * NSL * FB);
+                    if constexpr (SIDE == SIDE_OUT) {
+                        zero_tap |= valid && (tl[i][r] == 0.0f);
+                        w = scale(w, filter_factor(tl[i][r], a.div, Nf));
+                    }
+                    st_c(w, ro, j * CB, r * NSL * CB);
+                });
+            }
+        }
+    }
+    if (zero_tap && a.div && a.status) *a.status = 1;
 }
-extern "C" int transform_ragged_plan_destroy(tf_ragged_plan) { return TF_OK; }
-extern "C" int transform_ragged_execute(tf_ragged_plan, int32_t, const void *, const float *, void *,
-                                        const void *, float *, int32_t *, int32_t, void *)
+
+// ------------------------------------------------------------------ class table
+// radix plans of the length-K part inside the persistent kernel: radices of at
+// most 16 keep the shared register allocation (the maximum over classes) low
+template <int K> struct RKPlan { using type = typename KPlan<K>::type; };
+template <> struct RKPlan<512> { using type = Radices<8, 8, 8>; };
+template <> struct RKPlan<1024> { using type = Radices<16, 16, 4>; };
+
+template <int K, int M>
+struct RClass {
+    using PL = typename PrependM<M, typename RKPlan<K>::type>::type;
+    static constexpr int TB0 = pow2_floor(PL::max_nb());
+    static constexpr int TB = TB0 < 64 ? 64 : (TB0 > RT ? RT : TB0);
+    static constexpr int BPW = RT / TB;
+    static constexpr int lds() { return PL::count > 1 ? BPW * PL::total() * 8 : 0; }
+};
+
+#ifndef BT_RAGGED_CLASSES
+#define BT_RAGGED_CLASSES(X)                                                                          \
+    X(64, 3) X(64, 5) X(64, 7) X(64, 9) X(64, 15) X(128, 3) X(128, 5) X(128, 7) X(128, 9) X(128, 15) \
+    X(256, 3) X(256, 5) X(256, 7) X(256, 9) X(256, 15) X(512, 3) X(512, 5) X(512, 7) X(512, 9)      \
+    X(512, 15) X(1024, 3) X(1024, 5) X(1024, 7) X(1024, 9) X(1024, 15)
+#endif
+
+struct ClassInfo {
+    int K, M, N, TB, BPW, lds, npass;
+    int radix[8];
+};
+
+static const ClassInfo *class_table(int *count)
 {
-    return TF_EUNSUPPORTED;
+    static std::vector<ClassInfo> t = [] {
+        std::vector<ClassInfo> v;
+#define BT_CLASS_INFO(K_, M_)                                                               \
+    {                                                                                       \
+        using C = RClass<K_, M_>;                                                           \
+        ClassInfo c{K_, M_, K_ * M_, C::TB, C::BPW, C::lds(), C::PL::count, {}};            \
+        for (int i = 0; i < C::PL::count; ++i) c.radix[i] = C::PL::get(i);                  \
+        v.push_back(c);                                                                     \
+    }
+        BT_RAGGED_CLASSES(BT_CLASS_INFO)
+#undef BT_CLASS_INFO
+        return v;
+    }();
+    *count = (int)t.size();
+    return t.data();
+}
+
+template <int SIDE, bool TGR>
+__global__ void __launch_bounds__(RT) ragged_kernel(RaggedArgs a)
+{
+    extern __shared__ c32 lds_dyn[];
+    __shared__ int item_s;
+    for (;;) {
+        if (threadIdx.x == 0) item_s = atomicAdd(a.counter, 1);
+        __syncthreads();
+        const int item = item_s;
+        __syncthreads();
+        if (item >= a.nitems) break;     // every workgroup reaches this once the queue is empty
+        const RaggedItem it = a.items[item];
+        int cls = 0;
+#define BT_CLASS_CASE(K_, M_)                                                                      \
+    if (it.cls == cls) {                                                                           \
+        using C = RClass<K_, M_>;                                                                  \
+        ragged_tile<typename C::PL, C::TB, C::BPW, SIDE, TGR>(a, it, lds_dyn);                     \
+    }                                                                                              \
+    ++cls;
+        BT_RAGGED_CLASSES(BT_CLASS_CASE)
+#undef BT_CLASS_CASE
+    }
+}
+
+__global__ void ragged_reset_kernel(int *counter) { *counter = 0; }
+
+// ------------------------------------------------------------------ plan
+struct GraphKey {
+    int dir;
+    const void *in, *taps, *out, *aux, *tapbar, *status;
+    bool operator<(const GraphKey &o) const
+    {
+        return std::tie(dir, in, taps, out, aux, tapbar, status) <
+               std::tie(o.dir, o.in, o.taps, o.out, o.aux, o.tapbar, o.status);
+    }
+};
+
+} // namespace bt
+
+struct tf_ragged_plan_s {
+    int device = 0;
+    int64_t nblocks = 0;
+    int nitems = 0;
+    int max_lds = 0;
+    int grid[3] = {0, 0, 0};
+    int64_t *x_off = nullptr, *tap_off = nullptr;
+    int *order = nullptr;
+    bt::RaggedItem *items = nullptr;
+    bt::c32 *tw = nullptr;
+    int *tw_off = nullptr;
+    int *counter = nullptr;
+    hipStream_t capture_stream = nullptr;
+    std::map<bt::GraphKey, hipGraphExec_t> graphs;
+    std::mutex mu;
+};
+
+using namespace bt;
+
+static int fail(const char *what, hipError_t e)
+{
+    set_error(what, e);
+    return TF_EHIP;
+}
+
+static void plan_free(tf_ragged_plan p)
+{
+    if (!p) return;
+    for (auto &kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+    (void)hipFree(p->x_off);
+    (void)hipFree(p->tap_off);
+    (void)hipFree(p->order);
+    (void)hipFree(p->items);
+    (void)hipFree(p->tw);
+    (void)hipFree(p->tw_off);
+    (void)hipFree(p->counter);
+    if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+    delete p;
+}
+
+template <class T>
+static int upload_vec(const std::vector<T> &h, T **d)
+{
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(d), std::max<size_t>(h.size(), 1) * sizeof(T));
+    if (e != hipSuccess) return fail("hipMalloc(ragged plan)", e);
+    if (!h.empty()) {
+        e = hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return fail("hipMemcpy(ragged plan)", e);
+    }
+    return TF_OK;
+}
+
+static const void *ragged_kernel_ptr(int side, bool tg)
+{
+    if (side == SIDE_IN) return reinterpret_cast<const void *>(&ragged_kernel<SIDE_IN, false>);
+    return tg ? reinterpret_cast<const void *>(&ragged_kernel<SIDE_OUT, true>)
+              : reinterpret_cast<const void *>(&ragged_kernel<SIDE_OUT, false>);
+}
+
+extern "C" int transform_ragged_plan_create(const int32_t *K, const int32_t *M, const int64_t *x_off,
+                                            const int64_t *tap_off, int64_t nblocks,
+                                            int64_t total_points, tf_ragged_plan *plan)
+{
+    if (!plan) return TF_EINVAL;
+    *plan = nullptr;
+    if (nblocks < 0 || total_points < 0 || (nblocks > 0 && (!K || !M || !x_off || !tap_off)))
+        return TF_EINVAL;
+    if (nblocks > (int64_t(1) << 30)) return TF_EUNSUPPORTED;
+    int ncls = 0;
+    const ClassInfo *cls = class_table(&ncls);
+    std::map<std::pair<int, int>, int> cls_of;
+    for (int c = 0; c < ncls; ++c) cls_of[{cls[c].K, cls[c].M}] = c;
+
+    std::vector<std::vector<int>> members(ncls);
+    for (int64_t b = 0; b < nblocks; ++b) {
+        if (!supported_km(K[b], M[b])) return TF_EUNSUPPORTED;
+        auto f = cls_of.find({K[b], M[b]});
+        if (f == cls_of.end()) return TF_EUNSUPPORTED;
+        const int64_t N = int64_t(K[b]) * M[b];
+        if (x_off[b] < 0 || x_off[b] + N > total_points || tap_off[b] < 0) return TF_EINVAL;
+        members[f->second].push_back(int(b));
+    }
+    // tiles of same-class blocks, sorted by cost (largest first)
+    std::vector<int> order;
+    std::vector<RaggedItem> items;
+    std::vector<double> cost;
+    int max_lds = 0;
+    for (int c = 0; c < ncls; ++c) {
+        if (members[c].empty()) continue;
+        max_lds = std::max(max_lds, cls[c].lds);
+        for (size_t s = 0; s < members[c].size(); s += cls[c].BPW) {
+            RaggedItem it{};
+            it.cls = c;
+            it.first = int(order.size());
+            it.count = int(std::min<size_t>(cls[c].BPW, members[c].size() - s));
+            for (int q = 0; q < it.count; ++q) order.push_back(members[c][s + q]);
+            items.push_back(it);
+            cost.push_back(double(it.count) * cls[c].N * std::log2(double(cls[c].N)));
+        }
+    }
+    std::vector<int> perm(items.size());
+    for (size_t i = 0; i < perm.size(); ++i) perm[i] = int(i);
+    std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    std::vector<RaggedItem> sorted;
+    for (int i : perm) sorted.push_back(items[i]);
+
+    // base-root twiddle tables of every class (same layout as the uniform kernel)
+    std::vector<c32> tw;
+    std::vector<int> tw_off(ncls, 0);
+    for (int c = 0; c < ncls; ++c) {
+        tw_off[c] = int(tw.size());
+        long ns = cls[c].radix[0];
+        for (int p = 1; p < cls[c].npass; ++p) {
+            const long R = cls[c].radix[p];
+            for (long jm = 0; jm < ns; ++jm) {
+                const double ang = 2.0 * M_PI * double(jm) / double(ns * R);
+                tw.push_back(c32{float(std::cos(ang)), float(std::sin(ang))});
+            }
+            ns *= R;
+        }
+    }
+
+    tf_ragged_plan p = new tf_ragged_plan_s;
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        delete p;
+        return TF_EHIP;
+    }
+    p->nblocks = nblocks;
+    p->nitems = int(sorted.size());
+    p->max_lds = max_lds;
+    std::vector<int64_t> xo(x_off, x_off + nblocks), to(tap_off, tap_off + nblocks);
+    int rc = TF_OK;
+    if (!rc) rc = upload_vec(xo, &p->x_off);
+    if (!rc) rc = upload_vec(to, &p->tap_off);
+    if (!rc) rc = upload_vec(order, &p->order);
+    if (!rc) rc = upload_vec(sorted, &p->items);
+    if (!rc) rc = upload_vec(tw, &p->tw);
+    if (!rc) rc = upload_vec(tw_off, &p->tw_off);
+    if (!rc) rc = upload_vec(std::vector<int>{0}, &p->counter);
+    // persistent grid: the resident capacity for this LDS size, per kernel variant
+    int cus = 0;
+    if (!rc && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess)
+        rc = TF_EHIP;
+    for (int v = 0; v < 3 && !rc; ++v) {
+        const void *k = ragged_kernel_ptr(v == 0 ? SIDE_IN : SIDE_OUT, v == 2);
+        if (max_lds > 64 * 1024) {
+            hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+            if (e != hipSuccess) rc = fail("hipFuncSetAttribute", e);
+        }
+        int occ = 0;
+        if (!rc) {
+            hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, RT, max_lds);
+            if (e != hipSuccess) rc = fail("occupancy", e);
+        }
+        p->grid[v] = std::max(1, std::min(occ * cus, std::max(p->nitems, 1)));
+    }
+    if (!rc) {
+        hipError_t e = hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) rc = fail("hipStreamCreate", e);
+    }
+    if (rc) {
+        plan_free(p);
+        return rc;
+    }
+    *plan = p;
+    return TF_OK;
+}
+
+extern "C" int transform_ragged_plan_destroy(tf_ragged_plan plan)
+{
+    plan_free(plan);
+    return TF_OK;
+}
+
+static hipError_t ragged_launch(tf_ragged_plan p, int dir, const RaggedArgs &a, hipStream_t s)
+{
+    const int side = dir == 0 ? SIDE_IN : SIDE_OUT;
+    const bool tg = a.tapbar != nullptr;
+    const int v = dir == 0 ? 0 : (tg ? 2 : 1);
+    hipLaunchKernelGGL(ragged_reset_kernel, dim3(1), dim3(1), 0, s, a.counter);
+    if (side == SIDE_IN)
+        hipLaunchKernelGGL((ragged_kernel<SIDE_IN, false>), dim3(p->grid[v]), dim3(RT), p->max_lds, s, a);
+    else if (tg)
+        hipLaunchKernelGGL((ragged_kernel<SIDE_OUT, true>), dim3(p->grid[v]), dim3(RT), p->max_lds, s, a);
+    else
+        hipLaunchKernelGGL((ragged_kernel<SIDE_OUT, false>), dim3(p->grid[v]), dim3(RT), p->max_lds, s, a);
+    return hipGetLastError();
+}
+
+extern "C" int transform_ragged_execute(tf_ragged_plan plan, int32_t direction, const void *in,
+                                        const float *taps, void *out, const void *aux, float *taps_bar,
+                                        int32_t *status_dev, int32_t use_graph, void *stream)
+{
+    if (!plan || direction < 0 || direction > 2) return TF_EINVAL;
+    if (plan->nitems == 0) return TF_OK;
+    if (!in || !out || !taps) return TF_EINVAL;
+    if (in == out) return TF_EINVAL;
+    if (taps_bar && (direction != 2 || !aux)) return TF_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) % 8 ||
+        reinterpret_cast<uintptr_t>(taps) % 4)
+        return TF_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev != plan->device) return TF_EINVAL;
+    RaggedArgs a{};
+    a.in = reinterpret_cast<const c32 *>(in);
+    a.out = reinterpret_cast<c32 *>(out);
+    a.taps = taps;
+    a.aux = reinterpret_cast<const c32 *>(aux);
+    a.tapbar = taps_bar;
+    a.status = status_dev;
+    a.x_off = plan->x_off;
+    a.tap_off = plan->tap_off;
+    a.order = plan->order;
+    a.items = plan->items;
+    a.tw = plan->tw;
+    a.tw_off = plan->tw_off;
+    a.counter = plan->counter;
+    a.nitems = plan->nitems;
+    a.div = direction == 1;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> lk(plan->mu);
+    if (!use_graph) {
+        hipError_t e = ragged_launch(plan, direction, a, s);
+        return e == hipSuccess ? TF_OK : fail("ragged launch", e);
+    }
+    GraphKey key{direction, in, taps, out, aux, taps_bar, status_dev};
+    auto it = plan->graphs.find(key);
+    if (it == plan->graphs.end()) {
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ge = nullptr;
+        hipError_t e = hipStreamBeginCapture(plan->capture_stream, hipStreamCaptureModeRelaxed);
+        if (e != hipSuccess) return fail("hipStreamBeginCapture", e);
+        hipError_t le = ragged_launch(plan, direction, a, plan->capture_stream);
+        e = hipStreamEndCapture(plan->capture_stream, &g);
+        if (le != hipSuccess) return fail("ragged capture", le);
+        if (e != hipSuccess) return fail("hipStreamEndCapture", e);
+        e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return fail("hipGraphInstantiate", e);
+        it = plan->graphs.emplace(key, ge).first;
+    }
+    hipError_t e = hipGraphLaunch(it->second, s);
+    return e == hipSuccess ? TF_OK : fail("hipGraphLaunch", e);
 }

@@ -24,7 +24,7 @@ from . import _native as nat
 __all__ = [
     "transform_forward", "transform_inverse", "transform_adjoint", "transform_inverse_adjoint",
     "transform_prepare", "workspace_size", "schedules", "select_schedule", "Transform",
-    "InverseTransform", "forward", "inverse",
+    "InverseTransform", "forward", "inverse", "RaggedPlan",
 ]
 
 
@@ -213,3 +213,69 @@ def forward(S, taps, K, M):
 
 def inverse(y, taps, K, M):
     return InverseTransform.apply(y, taps, K, M)
+
+
+# ------------------------------------------------------------------ ragged batches
+class RaggedPlan:
+    """Persistent-kernel plan for a batch of blocks with their own (K, M).
+
+    `K`, `M`, `x_off`, `tap_off` are host arrays (one entry per block; offsets in
+    elements of the flat complex / tap arrays); `total_points` is the length of
+    the flat complex arrays.  The plan owns its device tables and HIP graphs.
+    """
+
+    DIRECTIONS = {"forward": 0, "inverse": 1, "adjoint": 2}
+
+    def __init__(self, K, M, x_off, tap_off, total_points: int):
+        import numpy as np
+        K = np.ascontiguousarray(K, dtype=np.int32)
+        M = np.ascontiguousarray(M, dtype=np.int32)
+        xo = np.ascontiguousarray(x_off, dtype=np.int64)
+        to = np.ascontiguousarray(tap_off, dtype=np.int64)
+        if not (K.shape == M.shape == xo.shape == to.shape):
+            raise ValueError("K, M, x_off, tap_off must have one entry per block")
+        self.total_points = int(total_points)
+        self.nblocks = int(K.size)
+        self._lib = nat.load()
+        h = ctypes.c_void_p()
+        nat.check("transform_ragged_plan_create", self._lib.transform_ragged_plan_create(
+            K.ctypes.data_as(ctypes.c_void_p), M.ctypes.data_as(ctypes.c_void_p),
+            xo.ctypes.data_as(ctypes.c_void_p), to.ctypes.data_as(ctypes.c_void_p),
+            self.nblocks, self.total_points, ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.transform_ragged_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def execute(self, direction: str, x: torch.Tensor, taps: torch.Tensor, *,
+                out: Optional[torch.Tensor] = None, aux: Optional[torch.Tensor] = None,
+                want_taps_bar: bool = False, status: Optional[torch.Tensor] = None,
+                use_graph: bool = True):
+        """direction: "forward" (x = S), "inverse" (x = y), "adjoint" (x = ybar; with
+        want_taps_bar, aux = S and the per-block tap gradient is returned laid out
+        like the coefficients)."""
+        d = self.DIRECTIONS[direction]
+        if x.dtype != torch.complex64 or x.dim() != 1 or x.numel() != self.total_points:
+            raise ValueError(f"x must be complex64 [{self.total_points}]")
+        if not x.is_contiguous() or not x.is_cuda:
+            raise ValueError("x must be a contiguous GPU tensor")
+        if taps.dtype != torch.float32 or not taps.is_contiguous() or taps.device != x.device:
+            raise ValueError("taps must be contiguous float32 on the same device")
+        out = torch.empty_like(x) if out is None else out
+        tb = None
+        if want_taps_bar:
+            if d != 2 or aux is None:
+                raise ValueError("the tap gradient is an adjoint output and needs aux = S")
+            tb = torch.empty(self.total_points, dtype=torch.float32, device=x.device)
+        nat.check("transform_ragged_execute", self._lib.transform_ragged_execute(
+            self._h, d, _ptr(x), _ptr(taps), _ptr(out), _ptr(aux), _ptr(tb), _ptr(status),
+            1 if use_graph else 0, _stream(x.device)))
+        return (out, tb) if want_taps_bar else out

@@ -1,0 +1,144 @@
+"""GPU parity of the ragged persistent kernel (one launch, HIP graph) against the oracle."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1604_06236_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((np.asarray(a, np.complex128) - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def per_block_max(a, b, lay):
+    worst = 0.0
+    for o, n in zip(lay.x_off, lay.N):
+        sl = slice(int(o), int(o + n))
+        worst = max(worst, float(np.linalg.norm(a[sl] - b[sl]) / np.linalg.norm(b[sl])))
+    return worst
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1604_06236_amd import transform
+    return transform
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_ragged_forward_inverse_adjoint(T, use_graph):
+    lay, S, taps = W.make_ragged("ragged", nblocks=260)      # every (K, M) class, ragged tail
+    print(f"case ragged blocks=260 graph={use_graph}", flush=True)
+    plan = T.RaggedPlan(lay.K, lay.M, lay.x_off, lay.tap_off, lay.total)
+    y_ref = O.forward_ragged(lay.N, lay.x_off, lay.tap_off, S, taps)
+    dS, dt = _dev(S), _dev(taps)
+    y = plan.execute("forward", dS, dt, use_graph=use_graph)
+    yh = _host(y)
+    assert rel_l2(yh, y_ref) < TOL and per_block_max(yh, y_ref, lay) < TOL
+    back = _host(plan.execute("inverse", y, dt, use_graph=use_graph))
+    assert rel_l2(back, S.astype(np.complex128)) < TOL
+    yb = W.cn01(np.random.default_rng(4), lay.total).astype(np.complex64)
+    sb_ref, tb_ref = O.adjoint_ragged(lay.N, lay.x_off, lay.tap_off, yb, taps, S)
+    sb, tb = plan.execute("adjoint", _dev(yb), dt, aux=dS, want_taps_bar=True, use_graph=use_graph)
+    assert rel_l2(_host(sb), sb_ref) < TOL
+    tbh = _host(tb).astype(np.float64)
+    assert float(np.linalg.norm(tbh - tb_ref) / np.linalg.norm(tb_ref)) < TOL
+    sb2 = plan.execute("adjoint", _dev(yb), dt, use_graph=use_graph)
+    assert rel_l2(_host(sb2), sb_ref) < TOL
+    plan.close()
+
+
+def test_ragged_graph_replays_match_eager(T):
+    """A captured graph replayed several times, with other work in between, gives
+    the eager result every time."""
+    import torch
+    lay, S, taps = W.make_ragged("ragged", nblocks=120)
+    plan = T.RaggedPlan(lay.K, lay.M, lay.x_off, lay.tap_off, lay.total)
+    dS, dt = _dev(S), _dev(taps)
+    eager = _host(plan.execute("forward", dS, dt, use_graph=False))
+    out = torch.empty_like(dS)
+    for rep in range(4):
+        out.zero_()
+        plan.execute("forward", dS, dt, out=out, use_graph=True)
+        got = _host(out)
+        assert np.array_equal(got.view(np.uint64), eager.view(np.uint64)), rep
+        _ = (dS * 2).sum()          # unrelated eager work between replays
+        torch.cuda.synchronize()
+    plan.close()
+
+
+def test_ragged_unsorted_offsets_and_gaps(T):
+    """Blocks listed out of memory order, with unused gaps between them."""
+    rng = np.random.default_rng(11)
+    Ks = rng.choice([64, 256, 1024], size=9).astype(np.int32)
+    Ms = rng.choice([3, 9, 15], size=9).astype(np.int32)
+    N = Ks.astype(np.int64) * Ms
+    perm = rng.permutation(9)
+    off = np.zeros(9, np.int64)
+    pos = 0
+    for b in perm:
+        pos += 16                          # gap
+        off[b] = pos
+        pos += N[b]
+    total = int(pos + 16)
+    S = W.qam(rng, 64, total).astype(np.complex64)
+    taps = np.ones(total, np.float32)
+    for b in range(9):
+        taps[off[b]:off[b] + N[b]] = W.rc_taps(int(N[b]), 0.4)
+    plan = T.RaggedPlan(Ks, Ms, off, off, total)
+    out = _dev(np.zeros(total, np.complex64))
+    y = _host(plan.execute("forward", _dev(S), _dev(taps), out=out))
+    ref = O.forward_ragged(N, off, off, S, taps)
+    for b in range(9):
+        sl = slice(int(off[b]), int(off[b] + N[b]))
+        assert rel_l2(y[sl], ref[sl]) < TOL
+    # gaps untouched
+    mask = np.ones(total, bool)
+    for b in range(9):
+        mask[off[b]:off[b] + N[b]] = False
+    assert np.all(y[mask] == 0)
+    plan.close()
+
+
+def test_ragged_full_batch_properties(T):
+    """The full 10,000-block batch: sampled blocks against the oracle, every block
+    through the inverse round trip."""
+    lay, S, taps = W.make_ragged("ragged")
+    print(f"case ragged full blocks={lay.K.size} points={lay.total}", flush=True)
+    plan = T.RaggedPlan(lay.K, lay.M, lay.x_off, lay.tap_off, lay.total)
+    dS, dt = _dev(S), _dev(taps)
+    y = plan.execute("forward", dS, dt)
+    back = _host(plan.execute("inverse", y, dt))
+    assert rel_l2(back, S.astype(np.complex128)) < TOL
+    idx = np.sort(np.random.default_rng(1).choice(lay.K.size, 40, replace=False))
+    sub = lay.subset(idx)
+    yh = _host(y)
+    Ssub = np.concatenate([S[int(lay.x_off[b]):int(lay.x_off[b] + lay.N[b])] for b in idx])
+    tsub = np.concatenate([taps[int(lay.tap_off[b]):int(lay.tap_off[b] + lay.N[b])] for b in idx])
+    ysub = np.concatenate([yh[int(lay.x_off[b]):int(lay.x_off[b] + lay.N[b])] for b in idx])
+    ref = O.forward_ragged(sub.N, sub.x_off, sub.tap_off, Ssub, tsub)
+    assert rel_l2(ysub, ref) < TOL
+    plan.close()
+
+
+def test_ragged_plan_rejects_bad_layouts(T):
+    from paper_1604_06236_amd._native import TransformError
+    with pytest.raises(TransformError):
+        T.RaggedPlan([48], [3], [0], [0], 144)          # K not a power of two
+    with pytest.raises(TransformError):
+        T.RaggedPlan([64], [3], [100], [0], 200)        # block runs past the end
