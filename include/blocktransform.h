@@ -70,6 +70,10 @@ typedef enum {
     TF_SPLIT_BF16 = 1,      /* stage DFTs as BF16 hi+lo MFMA GEMMs, FP32 accumulation */
     TF_SPLIT_FP16 = 2       /* stage DFTs as scaled FP16 hi+lo MFMA GEMMs, FP32 accumulation */
 } tf_compute;
+/* The split modes serve transform_forward and transform_adjoint (without
+   taps_bar) for K in {256, 1024}, M in [1, 16]; measured relative L2 against an
+   FP64 reference is about 6e-6 (BF16) and 2e-7 (FP16), bounded by
+   3 * 2^-2p * (4 + 2 sqrt(sqrt(K))) with p = 8 (BF16) or 11 (FP16). */
 
 /*
  * transform_forward -- y = T(S): y_u = sum_n Lambda_n S_n e^{+j 2 pi n u/N}
@@ -144,6 +148,9 @@ int transform_prepare(int32_t K, int32_t M, int32_t compute);
 /* Human-readable name of a tf_status value (static storage). */
 const char *transform_status_string(int status);
 
+/* Text of the last HIP error seen by the calling thread (after TF_EHIP). */
+const char *transform_last_error(void);
+
 /* ---------------------------------------------------------------- schedules
  * A (K, M) pair can run under several compiled schedules (radix plan, threads
  * per block, blocks per workgroup).  The autotuner times them and records the
@@ -159,6 +166,9 @@ int transform_schedule_describe(int32_t K, int32_t M, int32_t idx, char *buf, si
 /* Select schedule `idx` for (K, M) on all devices (idx -1: back to the default)
    and the grid cap in workgroups (0: automatic). */
 int transform_schedule_select(int32_t K, int32_t M, int32_t idx, int32_t grid_cap);
+
+/* The schedule index (0 = default) and grid cap currently selected for (K, M). */
+int transform_schedule_selected(int32_t K, int32_t M, int32_t *idx, int32_t *grid_cap);
 
 /* Load / save the selections as JSON ({"K,M": [idx, grid_cap], ...}). */
 int transform_load_schedule(const char *json_path);

@@ -31,6 +31,7 @@ EXPORTED = (
     "transform_workspace_size", "transform_prepare", "transform_status_string",
     "transform_last_error",
     "transform_schedule_count", "transform_schedule_describe", "transform_schedule_select",
+    "transform_schedule_selected",
     "transform_load_schedule", "transform_save_schedule",
     "transform_ragged_plan_create", "transform_ragged_plan_destroy", "transform_ragged_execute",
 )
@@ -71,6 +72,7 @@ def load() -> ctypes.CDLL:
     lib.transform_schedule_count.argtypes = [i32, i32]
     lib.transform_schedule_describe.argtypes = [i32, i32, i32, ctypes.c_char_p, sz]
     lib.transform_schedule_select.argtypes = [i32, i32, i32, i32]
+    lib.transform_schedule_selected.argtypes = [i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.transform_load_schedule.argtypes = [ctypes.c_char_p]
     lib.transform_save_schedule.argtypes = [ctypes.c_char_p]
     lib.transform_ragged_plan_create.argtypes = [vp, vp, vp, vp, i64, i64, ctypes.POINTER(vp)]

@@ -1,0 +1,84 @@
+"""Schedule autotuner for the fused kernels.
+
+For a block shape (K, M) the library compiles several schedules (radix plan,
+threads per block, blocks per workgroup, prefetch, twiddle form).  The tuner
+times forward + adjoint for each schedule and grid cap on synthetic batches of
+the given size, selects the fastest in the library and can save the choices as
+JSON ({"K,M": [schedule, grid_cap]}), which `transform` loads at import from
+$BT_SCHEDULES or from schedules.json next to this file.
+
+    python -m paper_1604_06236_amd.autotune --out schedules.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# (K, M, blocks) of the standard workloads, plus the classes of ragged batches
+STANDARD = [(16, 5, 65536), (128, 15, 4096), (256, 9, 8192), (1024, 15, 2048)]
+
+
+def tune_shape(T, K, M, B, caps=(0, 1024, 2048), reps=20, nbuf=2, verbose=True):
+    import torch
+    N = K * M
+    dev = "cuda"
+    taps = torch.rand(N, device=dev) + 0.5
+    sets = [(torch.randn(B, N, dtype=torch.complex64, device=dev),
+             torch.empty(B, N, dtype=torch.complex64, device=dev)) for _ in range(nbuf)]
+    results = []
+    for idx, desc in enumerate(T.schedules(K, M)):
+        for cap in caps:
+            T.select_schedule(K, M, idx, cap)
+            calls = [(T.bind_forward(x, taps, K, M, y), T.bind_adjoint(x, taps, K, M, y))
+                     for (x, y) in sets]
+            for i in range(3):
+                calls[i % nbuf][0]()
+                calls[i % nbuf][1]()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(reps):
+                calls[i % nbuf][0]()
+                calls[i % nbuf][1]()
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / reps
+            results.append({"schedule": idx, "grid_cap": cap, "us_fwd_adj": round(t * 1e6, 2),
+                            "GBps": round(2 * 16.0 * N * B / t / 1e9, 1), **desc})
+            if verbose:
+                print(f"K={K} M={M} sched={idx} cap={cap} {desc['radices']} TB={desc['threads_per_block']} "
+                      f"BPW={desc['blocks_per_workgroup']} pf={desc['prefetch']} "
+                      f"seq={desc['sequential_twiddles']}: {t * 1e6:.1f} us", flush=True)
+    best = min(results, key=lambda r: r["us_fwd_adj"])
+    T.select_schedule(K, M, best["schedule"], best["grid_cap"])
+    return best, results
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=None, help="write the selections here (JSON)")
+    ap.add_argument("--report", default=None, help="write every timing here (JSON)")
+    ap.add_argument("--reps", type=int, default=20)
+    args = ap.parse_args()
+    from paper_1604_06236_amd import transform as T
+    from paper_1604_06236_amd import _native as nat
+    report = {}
+    for K, M, B in STANDARD:
+        best, res = tune_shape(T, K, M, B, reps=args.reps)
+        report[f"{K},{M}"] = {"best": best, "all": res}
+        print(f"best for K={K} M={M}: schedule {best['schedule']} cap {best['grid_cap']} "
+              f"({best['us_fwd_adj']} us, {best['GBps']} GB/s)", flush=True)
+    if args.out:
+        nat.check("transform_save_schedule", nat.load().transform_save_schedule(args.out.encode()))
+    if args.report:
+        with open(args.report, "w") as f:
+            json.dump(report, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -513,8 +513,24 @@ extern "C" int transform_schedule_describe(int32_t K, int32_t M, int32_t idx, ch
     for (int i = 0; i < e.npass; ++i) rad += (i ? "," : "") + std::to_string(e.radix[i]);
     std::snprintf(buf, buflen,
                   "{\"K\": %d, \"M\": %d, \"radices\": [%s], \"threads_per_block\": %d, "
-                  "\"blocks_per_workgroup\": %d, \"lds_bytes\": %d}",
-                  e.K, e.M, rad.c_str(), e.TB, e.BPW, e.lds_bytes);
+                  "\"blocks_per_workgroup\": %d, \"lds_bytes\": %d, \"prefetch\": %s, "
+                  "\"sequential_twiddles\": %s}",
+                  e.K, e.M, rad.c_str(), e.TB, e.BPW, e.lds_bytes, (e.opt & OPT_NO_PREFETCH) ? "false" : "true",
+                  (e.opt & OPT_SEQ_TWIDDLE) ? "true" : "false");
+    return TF_OK;
+}
+
+extern "C" int transform_schedule_selected(int32_t K, int32_t M, int32_t *idx, int32_t *grid_cap)
+{
+    if (!supported_km(K, M) || !idx || !grid_cap) return TF_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    *idx = 0;
+    *grid_cap = 0;
+    auto s = g_select.find({K, M});
+    if (s != g_select.end()) {
+        *idx = s->second.idx < 0 ? 0 : s->second.idx;
+        *grid_cap = s->second.grid_cap;
+    }
     return TF_OK;
 }
 

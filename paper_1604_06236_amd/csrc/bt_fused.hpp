@@ -130,6 +130,39 @@ __device__ __forceinline__ void apply_twiddles(c32 (&v)[R], c32 w1)
     }
 }
 
+// the same with the powers formed one after another (two live registers, error
+// growing with r instead of log2 r)
+template <int R>
+__device__ __forceinline__ void apply_twiddles_seq(c32 (&v)[R], c32 w1)
+{
+    if constexpr (R > 1) {
+        c32 w = w1;
+        v[1] = cmul(v[1], w);
+        static_for<2, R>([&](auto rI) {
+            constexpr int r = decltype(rI)::value;
+            w = cmul(w, w1);
+            v[r] = cmul(v[r], w);
+        });
+    }
+}
+
+// schedule options
+enum : int {
+    OPT_NO_PREFETCH = 1,   // fetch each group when it is processed (fewer live registers)
+    OPT_SEQ_TWIDDLE = 2,   // sequential twiddle powers
+};
+
+template <int OPT, int R>
+__device__ __forceinline__ void twiddle(c32 (&v)[R], c32 w1)
+{
+    // The base root is loop-invariant across blocks; without this empty asm the
+    // compiler hoists all R-1 powers out of the block loop and keeps them live
+    // (spilling).  It emits no instruction.
+    asm volatile("" : "+v"(w1.x), "+v"(w1.y));
+    if constexpr (OPT & OPT_SEQ_TWIDDLE) apply_twiddles_seq<R>(v, w1);
+    else apply_twiddles<R>(v, w1);
+}
+
 // register slots of the base twiddles held by one thread: pass p >= 1 owns
 // IT_p consecutive slots
 template <class PL, int TB>
@@ -188,7 +221,7 @@ __device__ __forceinline__ float filter_factor(float t, int div, float Nf)
 }
 
 // ------------------------------------------------------------------ LDS passes
-template <class PL, int TB, int P>
+template <class PL, int TB, int P, int OPT = 0>
 __device__ __forceinline__ void lds_passes(c32 *L, int tid, const c32 *w1s)
 {
     if constexpr (P < PL::count - 1) {
@@ -207,7 +240,7 @@ __device__ __forceinline__ void lds_passes(c32 *L, int tid, const c32 *w1s)
                     constexpr int r = decltype(rI)::value;
                     v[i][r] = L[j + r * NB];
                 });
-                apply_twiddles<R>(v[i], w1s[SLOT + i]);
+                twiddle<OPT, R>(v[i], w1s[SLOT + i]);
                 dft<R>(v[i]);
             }
         }
@@ -225,12 +258,12 @@ __device__ __forceinline__ void lds_passes(c32 *L, int tid, const c32 *w1s)
             }
         }
         lds_barrier();
-        lds_passes<PL, TB, P + 1>(L, tid, w1s);
+        lds_passes<PL, TB, P + 1, OPT>(L, tid, w1s);
     }
 }
 
 // SIDE: where the filter applies (and the exponent sign); TGR: with the tap gradient
-template <class PL, int TB, int BPW, int SIDE, bool TGR>
+template <class PL, int TB, int BPW, int SIDE, bool TGR, int OPT>
 __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
 {
     constexpr int TG = !TGR ? 0 : (SIDE == SIDE_OUT ? 1 : 2);
@@ -315,9 +348,11 @@ __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
         }
     };
 
+    constexpr bool PREFETCH = !(OPT & OPT_NO_PREFETCH);
     int64_t g = blockIdx.x;
-    if (g < ngroups) fetch(g);
+    if (PREFETCH && g < ngroups) fetch(g);
     for (; g < ngroups; g += gridDim.x) {
+        if (!PREFETCH) fetch(g);
         const rsrc_t ro = rs_cplx(a.out, g);
         const rsrc_t rt = rs_taps(g);
         const uint32_t tb = shared_taps ? 0u : boff;
@@ -367,7 +402,7 @@ __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
                     });
                 }
             }
-            if (g + gridDim.x < ngroups) fetch(g + gridDim.x);
+            if (PREFETCH && g + gridDim.x < ngroups) fetch(g + gridDim.x);
         } else {
             // ---- pass 0 on the fetched operands: filter, length-R0 DFT (no twiddle, Ns = 1)
             c32 v0[IT0][R0];
@@ -406,7 +441,7 @@ __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
             }
             // ---- start reading the next group while this one runs in LDS, and the
             //      operands the last pass needs (output-side taps, S for the tap term)
-            if (g + gridDim.x < ngroups) fetch(g + gridDim.x);
+            if (PREFETCH && g + gridDim.x < ngroups) fetch(g + gridDim.x);
             float tl[SIDE == SIDE_OUT ? ITL : 1][SIDE == SIDE_OUT ? RL : 1];
             c32 sl[TG == TG_OUT_ ? ITL : 1][TG == TG_OUT_ ? RL : 1];
 #pragma unroll
@@ -423,7 +458,7 @@ __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
             lds_barrier();
 
             // ---- middle passes in LDS
-            lds_passes<PL, TB, 1>(L, tid, w1s);
+            lds_passes<PL, TB, 1, OPT>(L, tid, w1s);
 
             // ---- last pass: LDS -> registers -> twiddle -> DFT_RL -> HBM
             constexpr int SLOTL = TwSlots<PL, TB>::off(NP - 1);
@@ -436,7 +471,7 @@ __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
                         constexpr int r = decltype(rI)::value;
                         v[r] = L[j + r * NBL];
                     });
-                    apply_twiddles<RL>(v, w1s[SLOTL + i]);
+                    twiddle<OPT, RL>(v, w1s[SLOTL + i]);
                     dft<RL>(v);
                     static_for<0, RL>([&](auto rI) {
                         constexpr int r = decltype(rI)::value;
@@ -493,7 +528,7 @@ __global__ void tapgrad_reduce_kernel(const float *part, int64_t rows, int64_t n
 typedef hipError_t (*fused_launch_fn)(const FusedArgs &, unsigned grid, hipStream_t);
 
 struct FusedEntry {
-    int K, M, TB, BPW, npass;
+    int K, M, TB, BPW, npass, opt;
     int radix[8];
     int tw_entries;
     int lds_bytes;
@@ -501,14 +536,14 @@ struct FusedEntry {
     const void *kernel[2][2];         // for occupancy queries
 };
 
-template <class PL, int TB, int BPW, int SIDE, bool TGR>
+template <class PL, int TB, int BPW, int SIDE, bool TGR, int OPT>
 hipError_t fused_launch(const FusedArgs &a, unsigned grid, hipStream_t s)
 {
-    hipLaunchKernelGGL((fused_kernel<PL, TB, BPW, SIDE, TGR>), dim3(grid), dim3(TB * BPW), 0, s, a);
+    hipLaunchKernelGGL((fused_kernel<PL, TB, BPW, SIDE, TGR, OPT>), dim3(grid), dim3(TB * BPW), 0, s, a);
     return hipGetLastError();
 }
 
-template <class PL, int TB, int BPW>
+template <class PL, int TB, int BPW, int OPT = 0>
 FusedEntry make_entry(int K, int M)
 {
     static_assert(PL::total() <= 16384, "block too large");
@@ -522,14 +557,15 @@ FusedEntry make_entry(int K, int M)
     for (int i = 0; i < PL::count && i < 8; ++i) e.radix[i] = PL::get(i);
     e.tw_entries = PL::tw_total();
     e.lds_bytes = PL::count > 1 ? BPW * PL::total() * (int)sizeof(c32) : 0;
-    e.launch[0][0] = &fused_launch<PL, TB, BPW, SIDE_IN, false>;
-    e.launch[0][1] = &fused_launch<PL, TB, BPW, SIDE_IN, true>;
-    e.launch[1][0] = &fused_launch<PL, TB, BPW, SIDE_OUT, false>;
-    e.launch[1][1] = &fused_launch<PL, TB, BPW, SIDE_OUT, true>;
-    e.kernel[0][0] = reinterpret_cast<const void *>(&fused_kernel<PL, TB, BPW, SIDE_IN, false>);
-    e.kernel[0][1] = reinterpret_cast<const void *>(&fused_kernel<PL, TB, BPW, SIDE_IN, true>);
-    e.kernel[1][0] = reinterpret_cast<const void *>(&fused_kernel<PL, TB, BPW, SIDE_OUT, false>);
-    e.kernel[1][1] = reinterpret_cast<const void *>(&fused_kernel<PL, TB, BPW, SIDE_OUT, true>);
+    e.opt = OPT;
+    e.launch[0][0] = &fused_launch<PL, TB, BPW, SIDE_IN, false, OPT>;
+    e.launch[0][1] = &fused_launch<PL, TB, BPW, SIDE_IN, true, OPT>;
+    e.launch[1][0] = &fused_launch<PL, TB, BPW, SIDE_OUT, false, OPT>;
+    e.launch[1][1] = &fused_launch<PL, TB, BPW, SIDE_OUT, true, OPT>;
+    e.kernel[0][0] = reinterpret_cast<const void *>(&fused_kernel<PL, TB, BPW, SIDE_IN, false, OPT>);
+    e.kernel[0][1] = reinterpret_cast<const void *>(&fused_kernel<PL, TB, BPW, SIDE_IN, true, OPT>);
+    e.kernel[1][0] = reinterpret_cast<const void *>(&fused_kernel<PL, TB, BPW, SIDE_OUT, false, OPT>);
+    e.kernel[1][1] = reinterpret_cast<const void *>(&fused_kernel<PL, TB, BPW, SIDE_OUT, true, OPT>);
     return e;
 }
 

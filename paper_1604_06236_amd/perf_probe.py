@@ -1,0 +1,73 @@
+"""Run selected transforms a few times for profiling (rocprofv3 counters/traces).
+
+    python -m paper_1604_06236_amd.perf_probe --what forward --reps 5
+
+Also runs a device-to-device copy of a known size (--copy-mib), whose FETCH_SIZE
+and WRITE_SIZE readings calibrate the counters: the copy reads and writes exactly
+that many bytes.
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--what", default="forward",
+                    choices=["forward", "adjoint", "forward_adjoint", "ragged", "split_bf16",
+                             "split_fp16", "differentiation"])
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--copy-mib", type=int, default=256)
+    args = ap.parse_args()
+
+    import numpy as np
+    import torch
+    from paper_1604_06236_amd import transform as T
+    from paper_1604_06236_amd import workloads as W
+
+    dev = "cuda"
+    n = args.copy_mib * 1024 * 1024 // 4
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(args.reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+    if args.what == "ragged":
+        lay, S_h, taps_h = W.make_ragged("ragged")
+        plan = T.RaggedPlan(lay.K, lay.M, lay.x_off, lay.tap_off, lay.total)
+        S = torch.from_numpy(S_h).to(dev)
+        taps = torch.from_numpy(taps_h).to(dev)
+        for _ in range(args.reps):
+            y = plan.execute("forward", S, taps, use_graph=False)
+        torch.cuda.synchronize()
+        print(f"ragged: {args.reps} forward launches over {lay.K.size} blocks", flush=True)
+        return
+    cfg = {"split_bf16": "precision", "split_fp16": "precision",
+           "differentiation": "differentiation"}.get(args.what, "plain_gpu")
+    c = W.CONFIGS[cfg]
+    S_h, taps_h = W.make_uniform(c)
+    S = torch.from_numpy(S_h).to(dev)
+    taps = torch.from_numpy(taps_h).to(dev)
+    y = torch.empty_like(S)
+    compute = args.what if args.what.startswith("split") else "fp32"
+    for _ in range(args.reps):
+        if args.what in ("forward", "forward_adjoint", "split_bf16", "split_fp16", "differentiation"):
+            T.transform_forward(S, taps, c.K, c.M, out=y, compute=compute)
+        if args.what in ("adjoint", "forward_adjoint"):
+            T.transform_adjoint(S, taps, c.K, c.M, out=y)
+        if args.what == "differentiation":
+            T.transform_adjoint(y, taps, c.K, c.M, coeffs=S, want_taps_bar=True)
+    torch.cuda.synchronize()
+    print(f"{args.what}: {args.reps} reps on {cfg} ({c.nblocks} blocks, K={c.K}, M={c.M})", flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -21,10 +21,25 @@ import torch
 
 from . import _native as nat
 
+
+def load_schedules(path: Optional[str] = None) -> bool:
+    """Apply autotuned schedule choices from a JSON file ($BT_SCHEDULES, or
+    schedules.json next to this module).  Returns True when a file was applied."""
+    import os
+    path = path or os.environ.get("BT_SCHEDULES") or os.path.join(
+        os.path.dirname(os.path.abspath(__file__)), "schedules.json")
+    if not os.path.exists(path):
+        return False
+    return nat.load().transform_load_schedule(path.encode()) == nat.TF_OK
+
+
+load_schedules()
+
 __all__ = [
     "transform_forward", "transform_inverse", "transform_adjoint", "transform_inverse_adjoint",
     "transform_prepare", "workspace_size", "schedules", "select_schedule", "Transform",
-    "InverseTransform", "forward", "inverse", "RaggedPlan",
+    "InverseTransform", "forward", "inverse", "RaggedPlan", "bind_forward", "bind_adjoint",
+    "selected_schedule",
 ]
 
 
@@ -152,6 +167,48 @@ def transform_inverse_adjoint(coeffs_bar: torch.Tensor, taps: torch.Tensor, K: i
     return out, tb
 
 
+# ------------------------------------------------------------------ pre-marshalled calls
+class BoundCall:
+    """A transform call with every argument validated and marshalled once.
+
+    Calling it re-issues the same C-ABI call on the same tensors (the caller keeps
+    them alive), with only the stream looked up again; it is the low-overhead
+    path for loops that launch the same transform repeatedly."""
+
+    def __init__(self, fn_name: str, args: tuple, device, keep: tuple):
+        self._fn = getattr(nat.load(), fn_name)
+        self._name = fn_name
+        self._args = args
+        self._device = device
+        self._keep = keep                      # tensors the pointers refer to
+
+    def __call__(self):
+        nat.check(self._name, self._fn(*self._args, _stream(self._device)))
+
+
+def bind_forward(coeffs, taps, K, M, out, compute="fp32") -> BoundCall:
+    B = _check_blocks(coeffs, "coeffs", K, M)
+    _check_blocks(out, "samples", K, M)
+    ts = _tap_stride(taps, B, K * M, coeffs.device)
+    ws, wsb = _workspace(B, K, M, ts, compute, False, coeffs.device)
+    return BoundCall("transform_forward", (_ptr(coeffs), _ptr(taps), _ptr(out), B, K, M, ts,
+                                           _compute(compute), _ptr(ws), wsb),
+                     coeffs.device, (coeffs, taps, out, ws))
+
+
+def bind_adjoint(samples_bar, taps, K, M, out, coeffs=None, taps_bar=None, compute="fp32") -> BoundCall:
+    B = _check_blocks(samples_bar, "samples_bar", K, M)
+    _check_blocks(out, "coeffs_bar", K, M)
+    ts = _tap_stride(taps, B, K * M, samples_bar.device)
+    if taps_bar is not None and coeffs is None:
+        raise ValueError("the tap gradient needs coeffs")
+    ws, wsb = _workspace(B, K, M, ts, compute, taps_bar is not None, samples_bar.device)
+    return BoundCall("transform_adjoint", (_ptr(samples_bar), _ptr(taps), _ptr(coeffs), _ptr(out),
+                                           _ptr(taps_bar), B, K, M, ts, _compute(compute),
+                                           _ptr(ws), wsb),
+                     samples_bar.device, (samples_bar, taps, coeffs, out, taps_bar, ws))
+
+
 # ------------------------------------------------------------------ schedules
 def schedules(K: int, M: int):
     import json
@@ -162,6 +219,14 @@ def schedules(K: int, M: int):
         nat.check("transform_schedule_describe", lib.transform_schedule_describe(K, M, i, buf, 512))
         out.append(json.loads(buf.value.decode()))
     return out
+
+
+def selected_schedule(K: int, M: int):
+    """(index, grid cap, description) of the schedule currently used for (K, M)."""
+    i, c = ctypes.c_int32(), ctypes.c_int32()
+    nat.check("transform_schedule_selected", nat.load().transform_schedule_selected(
+        K, M, ctypes.byref(i), ctypes.byref(c)))
+    return i.value, c.value, schedules(K, M)[i.value]
 
 
 def select_schedule(K: int, M: int, idx: int, grid_cap: int = 0):
