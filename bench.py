@@ -98,30 +98,39 @@ def main():
     calls = [(T.bind_forward(S, taps, K, M, y), T.bind_adjoint(yb, taps, K, M, sb))
              for (S, y, yb, sb) in sets]
 
-    def step(i, ev=None):
+    def step(i):
         fwd, adj = calls[i % len(calls)]
-        if ev is not None:
-            ev[0].record()
         fwd()
-        if ev is not None:
-            ev[1].record()
         adj()
-        if ev is not None:
-            ev[2].record()
 
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     t0 = time.perf_counter()
     for i in range(args.steps):
-        step(i, events[i])
+        step(i)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in events]))
-    adj_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in events]))
     ms_per_step = wall * 1e3 / args.steps
     blocks_per_s = B / (ms_per_step * 1e-3)
+
+    # kernel durations: HIP events (on the launch stream) around runs of back-to-back
+    # launches of one kernel, rotating over the buffer sets
+    def kernel_ms(which, reps):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        for i in range(len(calls)):
+            calls[i][which]()
+        ev0.record()
+        for i in range(reps):
+            calls[i % len(calls)][which]()
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / reps
+
+    fwd_ms = kernel_ms(0, args.steps)
+    adj_ms = kernel_ms(1, args.steps)
+    step(0)
 
     # roofline of the forward kernel: algorithmic bytes = read S (8N) + write y (8N) per
     # block, plus the shared taps (4N) once per launch
@@ -132,12 +141,12 @@ def main():
                 "traffic": measured_traffic("fused_forward_128x15", fwd_bytes),
                 "kernel": "fused_kernel (forward), schedule %s" % json.dumps(T.selected_schedule(K, M)[2]),
                 "kernel_ms": round(fwd_ms, 5), "adjoint_kernel_ms": round(adj_ms, 5),
-                "algorithmic_bytes_per_launch": fwd_bytes}
+                "algorithmic_bytes_per_launch": fwd_bytes,
+                "timing": "HIP events around %d back-to-back launches per kernel" % args.steps}
 
     # error against the oracle on a seeded sample of blocks of the timed data
     from oracle import oracle as O
     S0, y0, yb0, sb0 = sets[0]
-    step(0)
     torch.cuda.synchronize()
     idx = np.sort(np.random.default_rng(0).choice(B, 48, replace=False))
     yh = y0.cpu().numpy()[idx]

@@ -55,7 +55,7 @@ struct RaggedArgs {
 // tile body of one class: up to BPW blocks, TB threads each (TB >= 64, so a
 // wave never straddles two blocks and block bases are wave-uniform)
 template <class PL, int TB, int BPW, int SIDE, bool TGR>
-__device__ __forceinline__ void ragged_tile(const RaggedArgs &a, const RaggedItem &it, c32 *lds)
+__device__ __attribute__((noinline)) void ragged_tile(const RaggedArgs &a, const RaggedItem &it, c32 *lds)
 {
     static_assert(TB * BPW == RT, "tile must fill the workgroup");
     static_assert(TB >= 64, "a wave must stay inside one block");
@@ -178,7 +178,7 @@ __device__ __forceinline__ void ragged_tile(const RaggedArgs &a, const RaggedIte
             }
         }
         lds_barrier();
-        lds_passes<PL, TB, 1>(L, tid, w1s);
+        lds_passes<PL, TB, 1, OPT_SEQ_TWIDDLE>(L, tid, w1s);
         constexpr int SLOTL = TwSlots<PL, TB>::off(NP - 1);
 #pragma unroll
         for (int i = 0; i < ITL; ++i) {
@@ -189,7 +189,7 @@ __device__ __forceinline__ void ragged_tile(const RaggedArgs &a, const RaggedIte
                     constexpr int r = decltype(rI)::value;
                     v[r] = L[j + r * NBL];
                 });
-                apply_twiddles<RL>(v, w1s[SLOTL + i]);
+                twiddle<OPT_SEQ_TWIDDLE, RL>(v, w1s[SLOTL + i]);
                 dft<RL>(v);
                 static_for<0, RL>([&](auto rI) {
                     constexpr int r = decltype(rI)::value;

@@ -171,19 +171,21 @@ def transform_inverse_adjoint(coeffs_bar: torch.Tensor, taps: torch.Tensor, K: i
 class BoundCall:
     """A transform call with every argument validated and marshalled once.
 
-    Calling it re-issues the same C-ABI call on the same tensors (the caller keeps
-    them alive), with only the stream looked up again; it is the low-overhead
-    path for loops that launch the same transform repeatedly."""
+    Calling it re-issues the same C-ABI call on the same tensors (kept alive by
+    the object) on the stream that was current when it was bound; it is the
+    low-overhead path for loops that launch the same transform repeatedly."""
 
     def __init__(self, fn_name: str, args: tuple, device, keep: tuple):
         self._fn = getattr(nat.load(), fn_name)
         self._name = fn_name
-        self._args = args
-        self._device = device
+        # the stream current at bind time is the one every call launches on
+        self._args = args + (_stream(device),)
         self._keep = keep                      # tensors the pointers refer to
 
     def __call__(self):
-        nat.check(self._name, self._fn(*self._args, _stream(self._device)))
+        rc = self._fn(*self._args)
+        if rc:
+            nat.check(self._name, rc)
 
 
 def bind_forward(coeffs, taps, K, M, out, compute="fp32") -> BoundCall:
