@@ -25,7 +25,7 @@ if ROOT not in sys.path:
 STANDARD = [(16, 5, 65536), (128, 15, 4096), (256, 9, 8192), (1024, 15, 2048)]
 
 
-def tune_shape(T, K, M, B, caps=(0, 1024, 2048), reps=20, nbuf=2, verbose=True):
+def tune_shape(T, K, M, B, caps=(0, 1024, 2048), reps=20, nbuf=4, verbose=True):
     import torch
     N = K * M
     dev = "cuda"

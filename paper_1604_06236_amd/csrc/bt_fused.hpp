@@ -150,6 +150,8 @@ __device__ __forceinline__ void apply_twiddles_seq(c32 (&v)[R], c32 w1)
 enum : int {
     OPT_NO_PREFETCH = 1,   // fetch each group when it is processed (fewer live registers)
     OPT_SEQ_TWIDDLE = 2,   // sequential twiddle powers
+    OPT_PAIRED_IO = 4,     // first/last pass: a thread owns two adjacent butterflies (16-byte I/O)
+    OPT_NT = 8,            // non-temporal hint on the streaming HBM loads and stores
 };
 
 template <int OPT, int R>
@@ -163,11 +165,32 @@ __device__ __forceinline__ void twiddle(c32 (&v)[R], c32 w1)
     else apply_twiddles<R>(v, w1);
 }
 
+// Butterflies of pass p handled by one thread.  Plain: j = tid + i TB.  With
+// OPT_PAIRED_IO the first and last passes give each thread two adjacent
+// butterflies, j = 2 (tid + (i/2) TB) + (i%2), so their HBM accesses pair up
+// into 16-byte loads and stores.
+template <class PL, int TB, int OPT>
+struct Map {
+    static constexpr bool paired(int p) { return (OPT & OPT_PAIRED_IO) && (p == 0 || p == PL::count - 1); }
+    static constexpr int nb(int p) { return PL::total() / PL::get(p); }
+    static constexpr int it(int p)
+    {
+        return paired(p) ? 2 * ((nb(p) + 2 * TB - 1) / (2 * TB)) : (nb(p) + TB - 1) / TB;
+    }
+    static constexpr bool full(int p) { return paired(p) ? (it(p) * TB == nb(p)) : (it(p) * TB == nb(p)); }
+    template <int P>
+    __device__ static __forceinline__ int j(int tid, int i)
+    {
+        if constexpr (paired(P)) return 2 * (tid + (i >> 1) * TB) + (i & 1);
+        else return tid + i * TB;
+    }
+};
+
 // register slots of the base twiddles held by one thread: pass p >= 1 owns
-// IT_p consecutive slots
-template <class PL, int TB>
+// Map::it(p) consecutive slots
+template <class PL, int TB, int OPT = 0>
 struct TwSlots {
-    static constexpr int it(int p) { return (PL::total() / PL::get(p) + TB - 1) / TB; }
+    static constexpr int it(int p) { return Map<PL, TB, OPT>::it(p); }
     static constexpr int off(int p)
     {
         int o = 0;
@@ -190,9 +213,21 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint32_t bytes)
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, kRsrcWord3);
 }
 
+template <int AUX = 0>
 __device__ __forceinline__ c32 ld_c(rsrc_t r, uint32_t voff, uint32_t soff)
 {
-    return __builtin_bit_cast(c32, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    return __builtin_bit_cast(c32, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX));
+}
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+struct c32x2 {
+    c32 a, b;
+};
+
+template <int AUX = 0>
+__device__ __forceinline__ c32x2 ld_c2(rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(c32x2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, AUX));
 }
 
 __device__ __forceinline__ float ld_f(rsrc_t r, uint32_t voff, uint32_t soff)
@@ -202,9 +237,25 @@ __device__ __forceinline__ float ld_f(rsrc_t r, uint32_t voff, uint32_t soff)
 
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
+template <int AUX = 0>
 __device__ __forceinline__ void st_c(c32 v, rsrc_t r, uint32_t voff, uint32_t soff)
 {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, AUX);
+}
+
+template <int AUX = 0>
+__device__ __forceinline__ void st_c2(c32 a, c32 b, rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, c32x2{a, b}), r, voff, soff, AUX);
+}
+
+struct f32x2 {
+    float a, b;
+};
+
+__device__ __forceinline__ f32x2 ld_f2(rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
 }
 
 __device__ __forceinline__ void st_f(float v, rsrc_t r, uint32_t voff, uint32_t soff)
@@ -230,7 +281,7 @@ __device__ __forceinline__ void lds_passes(c32 *L, int tid, const c32 *w1s)
         constexpr int NS = PL::ns(P);
         constexpr int NB = N / R;
         constexpr int IT = (NB + TB - 1) / TB;
-        constexpr int SLOT = TwSlots<PL, TB>::off(P);
+        constexpr int SLOT = TwSlots<PL, TB, OPT>::off(P);
         c32 v[IT][R];
 #pragma unroll
         for (int i = 0; i < IT; ++i) {
@@ -272,17 +323,24 @@ __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
     constexpr int NP = PL::count;
     constexpr int R0 = PL::get(0);
     constexpr int NB0 = N / R0;
-    constexpr int IT0 = (NB0 + TB - 1) / TB;
+    using MP = Map<PL, TB, OPT>;
+    constexpr int IT0 = MP::it(0);
     constexpr int RL = PL::get(NP - 1);
     constexpr int NSL = PL::ns(NP - 1);
     constexpr int NBL = N / RL;
-    constexpr int ITL = (NBL + TB - 1) / TB;
+    constexpr int ITL = MP::it(NP - 1);
     constexpr bool FULL0 = IT0 * TB == NB0;
     constexpr bool FULLL = ITL * TB == NBL;
+    constexpr bool PAIR0 = MP::paired(0) && NP > 1;
+    constexpr bool PAIRL = MP::paired(NP - 1) && NP > 1;
     constexpr int NACC = TG == TG_OUT_ ? ITL * RL : (TG == TG_IN_ ? IT0 * R0 : 1);
     constexpr bool CONJ = SIDE == SIDE_OUT;
     constexpr uint32_t CB = 8;      // bytes per complex
     constexpr uint32_t FB = 4;      // bytes per tap
+    constexpr int NTA = (OPT & OPT_NT) ? 2 : 0;   // cache policy of the streaming accesses
+    static_assert(!(OPT & OPT_PAIRED_IO) || NP > 1, "paired I/O needs at least two passes");
+    static_assert(!PAIR0 || NB0 % 2 == 0, "paired I/O needs an even butterfly count");
+    static_assert(!PAIRL || NBL % 2 == 0, "paired I/O needs an even butterfly count");
 
     __shared__ c32 lds[NP > 1 ? BPW * N : 1];
     const int bi = threadIdx.x / TB;
@@ -300,16 +358,16 @@ __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
     for (int q = 0; q < NACC; ++q) acc[q] = 0.0f;
 
     // base twiddles of every pass >= 1, held for the whole kernel
-    c32 w1s[TwSlots<PL, TB>::total()];
+    c32 w1s[TwSlots<PL, TB, OPT>::total()];
     if constexpr (NP > 1) {
         static_for<1, NP>([&](auto pI) {
             constexpr int P = decltype(pI)::value;
             constexpr int NB = N / PL::get(P);
-            constexpr int IT = TwSlots<PL, TB>::it(P);
+            constexpr int IT = TwSlots<PL, TB, OPT>::it(P);
 #pragma unroll
             for (int i = 0; i < IT; ++i) {
-                const int j = tid + i * TB;
-                w1s[TwSlots<PL, TB>::off(P) + i] =
+                const int j = MP::template j<P>(tid, i);
+                w1s[TwSlots<PL, TB, OPT>::off(P) + i] =
                     (j < NB) ? a.tw[PL::tw_off(P) + j % PL::ns(P)] : c32{1.f, 0.f};
             }
         });
@@ -335,15 +393,35 @@ __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
         const rsrc_t ri = rs_cplx(a.in, g);
         const rsrc_t rt = rs_taps(g);
         const uint32_t tb = shared_taps ? 0u : boff;
+        if constexpr (PAIR0) {
 #pragma unroll
-        for (int i = 0; i < IT0; ++i) {
-            const int j = tid + i * TB;
-            if (FULL0 || j < NB0) {
-                static_for<0, R0>([&](auto rI) {
-                    constexpr int r = decltype(rI)::value;
-                    x0[i][r] = ld_c(ri, (boff + j) * CB, r * NB0 * CB);
-                    if constexpr (SIDE == SIDE_IN) t0[i][r] = ld_f(rt, (tb + j) * FB, r * NB0 * FB);
-                });
+            for (int i = 0; i < IT0; i += 2) {
+                const int j = MP::template j<0>(tid, i);
+                if (FULL0 || j < NB0) {
+                    static_for<0, R0>([&](auto rI) {
+                        constexpr int r = decltype(rI)::value;
+                        const c32x2 p = ld_c2<NTA>(ri, (boff + j) * CB, r * NB0 * CB);
+                        x0[i][r] = p.a;
+                        x0[i + 1][r] = p.b;
+                        if constexpr (SIDE == SIDE_IN) {
+                            const f32x2 t = ld_f2(rt, (tb + j) * FB, r * NB0 * FB);
+                            t0[i][r] = t.a;
+                            t0[i + 1][r] = t.b;
+                        }
+                    });
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < IT0; ++i) {
+                const int j = MP::template j<0>(tid, i);
+                if (FULL0 || j < NB0) {
+                    static_for<0, R0>([&](auto rI) {
+                        constexpr int r = decltype(rI)::value;
+                        x0[i][r] = ld_c<NTA>(ri, (boff + j) * CB, r * NB0 * CB);
+                        if constexpr (SIDE == SIDE_IN) t0[i][r] = ld_f(rt, (tb + j) * FB, r * NB0 * FB);
+                    });
+                }
             }
         }
     };
@@ -408,7 +486,7 @@ __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
             c32 v0[IT0][R0];
 #pragma unroll
             for (int i = 0; i < IT0; ++i) {
-                const int j = tid + i * TB;
+                const int j = MP::template j<0>(tid, i);
                 if (FULL0 || j < NB0) {
                     static_for<0, R0>([&](auto rI) {
                         constexpr int r = decltype(rI)::value;
@@ -431,7 +509,7 @@ __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
             lds_barrier();   // the previous group's last pass has finished reading LDS
 #pragma unroll
             for (int i = 0; i < IT0; ++i) {
-                const int j = tid + i * TB;
+                const int j = MP::template j<0>(tid, i);
                 if (FULL0 || j < NB0) {
                     static_for<0, R0>([&](auto rI) {
                         constexpr int r = decltype(rI)::value;
@@ -446,7 +524,7 @@ __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
             c32 sl[TG == TG_OUT_ ? ITL : 1][TG == TG_OUT_ ? RL : 1];
 #pragma unroll
             for (int i = 0; i < ITL; ++i) {
-                const int j = tid + i * TB;
+                const int j = MP::template j<NP - 1>(tid, i);
                 if (FULLL || j < NBL) {
                     static_for<0, RL>([&](auto rI) {
                         constexpr int r = decltype(rI)::value;
@@ -461,31 +539,40 @@ __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
             lds_passes<PL, TB, 1, OPT>(L, tid, w1s);
 
             // ---- last pass: LDS -> registers -> twiddle -> DFT_RL -> HBM
-            constexpr int SLOTL = TwSlots<PL, TB>::off(NP - 1);
+            constexpr int SLOTL = TwSlots<PL, TB, OPT>::off(NP - 1);
+            constexpr int STEP = PAIRL ? 2 : 1;
 #pragma unroll
-            for (int i = 0; i < ITL; ++i) {
-                const int j = tid + i * TB;
+            for (int i = 0; i < ITL; i += STEP) {
+                const int j = MP::template j<NP - 1>(tid, i);
                 if (FULLL || j < NBL) {
-                    c32 v[RL];
+                    c32 v[STEP][RL];
+#pragma unroll
+                    for (int h = 0; h < STEP; ++h) {
+                        static_for<0, RL>([&](auto rI) {
+                            constexpr int r = decltype(rI)::value;
+                            v[h][r] = L[j + h + r * NBL];
+                        });
+                        twiddle<OPT, RL>(v[h], w1s[SLOTL + i + h]);
+                        dft<RL>(v[h]);
+                    }
                     static_for<0, RL>([&](auto rI) {
                         constexpr int r = decltype(rI)::value;
-                        v[r] = L[j + r * NBL];
-                    });
-                    twiddle<OPT, RL>(v, w1s[SLOTL + i]);
-                    dft<RL>(v);
-                    static_for<0, RL>([&](auto rI) {
-                        constexpr int r = decltype(rI)::value;
-                        c32 w = CONJ ? conj(v[r]) : v[r];
-                        if constexpr (TG == TG_OUT_) {
-                            const float tg = sl[i][r].x * w.x + sl[i][r].y * w.y;
-                            if (shared_taps) acc[i * RL + r] += tg;
-                            else st_f(tg, rg, (boff + j) * FB, r * NSL * FB);
+                        c32 w[STEP];
+#pragma unroll
+                        for (int h = 0; h < STEP; ++h) {
+                            w[h] = CONJ ? conj(v[h][r]) : v[h][r];
+                            if constexpr (TG == TG_OUT_) {
+                                const float tg = sl[i + h][r].x * w[h].x + sl[i + h][r].y * w[h].y;
+                                if (shared_taps) acc[(i + h) * RL + r] += tg;
+                                else st_f(tg, rg, (boff + j + h) * FB, r * NSL * FB);
+                            }
+                            if constexpr (SIDE == SIDE_OUT) {
+                                zero_tap |= (tl[i + h][r] == 0.0f);
+                                w[h] = scale(w[h], filter_factor(tl[i + h][r], a.div, Nf));
+                            }
                         }
-                        if constexpr (SIDE == SIDE_OUT) {
-                            zero_tap |= (tl[i][r] == 0.0f);
-                            w = scale(w, filter_factor(tl[i][r], a.div, Nf));
-                        }
-                        st_c(w, ro, (boff + j) * CB, r * NSL * CB);
+                        if constexpr (PAIRL) st_c2<NTA>(w[0], w[1], ro, (boff + j) * CB, r * NSL * CB);
+                        else st_c<NTA>(w[0], ro, (boff + j) * CB, r * NSL * CB);
                     });
                 }
             }
@@ -501,7 +588,7 @@ __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
             if constexpr (TG == TG_IN_ || NP == 1) {
 #pragma unroll
                 for (int i = 0; i < IT0; ++i) {
-                    const int j = tid + i * TB;
+                    const int j = MP::template j<0>(tid, i);
                     if (FULL0 || j < NB0) {
 #pragma unroll
                         for (int r = 0; r < R0; ++r) row[j + r * NB0] = acc[i * R0 + r];
@@ -510,7 +597,7 @@ __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
             } else {
 #pragma unroll
                 for (int i = 0; i < ITL; ++i) {
-                    const int j = tid + i * TB;
+                    const int j = MP::template j<NP - 1>(tid, i);
                     if (FULLL || j < NBL) {
 #pragma unroll
                         for (int r = 0; r < RL; ++r) row[j + r * NSL] = acc[i * RL + r];

@@ -33,6 +33,16 @@ void register_fused_tuned(std::vector<FusedEntry> &v)
         // K = 128, M = 15 and K = 256, M = 9 with sequential twiddles
         make_entry<Radices<15, 16, 8>, 128, 1, OPT_SEQ_TWIDDLE>(128, 15),
         make_entry<Radices<9, 16, 16>, 256, 1, OPT_SEQ_TWIDDLE>(256, 9),
+        // 16-byte I/O (two adjacent butterflies per thread at the HBM ends), non-temporal
+        make_entry<Radices<15, 16, 8>, 64, 2, OPT_SEQ_TWIDDLE | OPT_PAIRED_IO>(128, 15),
+        make_entry<Radices<15, 16, 8>, 64, 1, OPT_SEQ_TWIDDLE | OPT_PAIRED_IO>(128, 15),
+        make_entry<Radices<15, 16, 8>, 128, 1, OPT_SEQ_TWIDDLE | OPT_NT>(128, 15),
+        make_entry<Radices<15, 16, 8>, 64, 2, OPT_SEQ_TWIDDLE | OPT_PAIRED_IO | OPT_NT>(128, 15),
+        make_entry<Radices<15, 8, 16>, 64, 2, OPT_SEQ_TWIDDLE | OPT_PAIRED_IO>(128, 15),
+        make_entry<Radices<9, 16, 16>, 128, 2, OPT_SEQ_TWIDDLE | OPT_PAIRED_IO>(256, 9),
+        make_entry<Radices<9, 16, 16>, 128, 1, OPT_SEQ_TWIDDLE | OPT_PAIRED_IO>(256, 9),
+        make_entry<Radices<9, 16, 16>, 256, 1, OPT_SEQ_TWIDDLE | OPT_NT>(256, 9),
+        make_entry<Radices<5, 4, 4>, 16, 8, OPT_PAIRED_IO>(16, 5),
     };
     v.insert(v.end(), e, e + sizeof(e) / sizeof(e[0]));
 }

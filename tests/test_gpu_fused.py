@@ -131,6 +131,14 @@ def test_all_schedules_agree(T):
                                          coeffs=_dev(S), want_taps_bar=True)
             sb_ref, tb_ref = O.adjoint(y_ref.astype(np.complex64), taps, S)
             assert rel_l2(_host(yb), sb_ref) < TOL and rel_l2(_host(tb), tb_ref) < TOL
+            yb2, _ = T.transform_adjoint(_dev(y_ref.astype(np.complex64)), _dev(taps), K, M)
+            assert rel_l2(_host(yb2), sb_ref) < TOL
+            back = _host(T.transform_inverse(_dev(y_ref.astype(np.complex64)), _dev(taps), K, M))
+            assert rel_l2(back, O.inverse(y_ref.astype(np.complex64), taps)) < TOL
+            g, tb2 = T.transform_inverse_adjoint(_dev(y_ref.astype(np.complex64)), _dev(taps), K, M,
+                                                 coeffs=_dev(S), want_taps_bar=True)
+            g_ref, tb2_ref = O.inverse_adjoint(y_ref.astype(np.complex64), taps, S)
+            assert rel_l2(_host(g), g_ref) < TOL and rel_l2(_host(tb2), tb2_ref) < TOL
         T.select_schedule(K, M, -1)
 
 
