@@ -188,6 +188,13 @@ typedef struct tf_ragged_plan_s *tf_ragged_plan;
 int transform_ragged_plan_create(const int32_t *K, const int32_t *M, const int64_t *x_off,
                                  const int64_t *tap_off, int64_t nblocks, int64_t total_points,
                                  tf_ragged_plan *plan);
+/* The same with an explicit work-item size: each item is `chunk_tiles` tiles
+   (a tile fills one workgroup with blocks of one class); 0 picks about eight
+   items per resident workgroup.  Larger items pipeline better, smaller ones
+   balance better; the autotuner chooses. */
+int transform_ragged_plan_create_ex(const int32_t *K, const int32_t *M, const int64_t *x_off,
+                                    const int64_t *tap_off, int64_t nblocks, int64_t total_points,
+                                    int32_t chunk_tiles, tf_ragged_plan *plan);
 int transform_ragged_plan_destroy(tf_ragged_plan plan);
 
 /* direction: 0 forward, 1 inverse, 2 adjoint (taps_bar per block, nullable; needs aux = S).

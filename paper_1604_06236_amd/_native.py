@@ -33,7 +33,8 @@ EXPORTED = (
     "transform_schedule_count", "transform_schedule_describe", "transform_schedule_select",
     "transform_schedule_selected",
     "transform_load_schedule", "transform_save_schedule",
-    "transform_ragged_plan_create", "transform_ragged_plan_destroy", "transform_ragged_execute",
+    "transform_ragged_plan_create", "transform_ragged_plan_create_ex", "transform_ragged_plan_destroy",
+    "transform_ragged_execute",
 )
 
 _lib = None
@@ -76,6 +77,7 @@ def load() -> ctypes.CDLL:
     lib.transform_load_schedule.argtypes = [ctypes.c_char_p]
     lib.transform_save_schedule.argtypes = [ctypes.c_char_p]
     lib.transform_ragged_plan_create.argtypes = [vp, vp, vp, vp, i64, i64, ctypes.POINTER(vp)]
+    lib.transform_ragged_plan_create_ex.argtypes = [vp, vp, vp, vp, i64, i64, i32, ctypes.POINTER(vp)]
     lib.transform_ragged_plan_destroy.argtypes = [vp]
     lib.transform_ragged_execute.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, i32, vp]
     for name in EXPORTED:

@@ -59,6 +59,39 @@ def tune_shape(T, K, M, B, caps=(0, 1024, 2048), reps=20, nbuf=4, verbose=True):
     return best, results
 
 
+def tune_ragged(T, W, chunks=(0, 1, 2, 4, 8, 16), reps=10, verbose=True):
+    """Time forward + adjoint of the standard ragged batch for several work-item
+    sizes (tiles per item); returns the best size."""
+    import numpy as np
+    import torch
+    lay, S_h, taps_h = W.make_ragged("ragged")
+    S = torch.from_numpy(S_h).cuda()
+    taps = torch.from_numpy(taps_h).cuda()
+    yb = torch.randn(lay.total, dtype=torch.complex64, device="cuda")
+    y = torch.empty_like(S)
+    sb = torch.empty_like(S)
+    results = []
+    for c in chunks:
+        plan = T.RaggedPlan(lay.K, lay.M, lay.x_off, lay.tap_off, lay.total, chunk_tiles=c)
+        for _ in range(2):
+            plan.execute("forward", S, taps, out=y)
+            plan.execute("adjoint", yb, taps, out=sb)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            plan.execute("forward", S, taps, out=y)
+            plan.execute("adjoint", yb, taps, out=sb)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / reps
+        plan.close()
+        results.append({"chunk_tiles": c, "us_fwd_adj": round(t * 1e6, 1),
+                        "GBps": round(2 * 20.0 * lay.total / t / 1e9, 1)})
+        if verbose:
+            print(f"ragged chunk_tiles={c}: {t * 1e6:.1f} us", flush=True)
+    best = min(results, key=lambda r: r["us_fwd_adj"])
+    return best, results
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=None, help="write the selections here (JSON)")
@@ -73,8 +106,18 @@ def main():
         report[f"{K},{M}"] = {"best": best, "all": res}
         print(f"best for K={K} M={M}: schedule {best['schedule']} cap {best['grid_cap']} "
               f"({best['us_fwd_adj']} us, {best['GBps']} GB/s)", flush=True)
+    from paper_1604_06236_amd import workloads as W
+    best_r, res_r = tune_ragged(T, W)
+    report["ragged"] = {"best": best_r, "all": res_r}
+    print(f"best for ragged: chunk_tiles {best_r['chunk_tiles']} ({best_r['us_fwd_adj']} us, "
+          f"{best_r['GBps']} GB/s)", flush=True)
     if args.out:
         nat.check("transform_save_schedule", nat.load().transform_save_schedule(args.out.encode()))
+        with open(args.out) as f:
+            sel = json.load(f)
+        sel["ragged_chunk_tiles"] = best_r["chunk_tiles"]
+        with open(args.out, "w") as f:
+            json.dump(sel, f, indent=1)
     if args.report:
         with open(args.report, "w") as f:
             json.dump(report, f, indent=1)

@@ -30,7 +30,7 @@ constexpr int RT = 1024;  // threads per workgroup of the persistent kernel
 struct RaggedItem {
     int cls;              // class index
     int first;            // first entry in the block order
-    int count;            // blocks in this tile (<= BPW of the class)
+    int count;            // blocks in this chunk (tiles of BPW blocks of the class)
     int pad;
 };
 
@@ -52,10 +52,12 @@ struct RaggedArgs {
     int div;
 };
 
-// tile body of one class: up to BPW blocks, TB threads each (TB >= 64, so a
-// wave never straddles two blocks and block bases are wave-uniform)
-template <class PL, int TB, int BPW, int SIDE, bool TGR>
-__device__ __attribute__((noinline)) void ragged_tile(const RaggedArgs &a, const RaggedItem &it, c32 *lds)
+// Chunk body of one class: `it.count` blocks (order[it.first ...]) processed as
+// tiles of up to BPW blocks, TB threads per block (TB >= 64, so a wave never
+// straddles two blocks and block bases are wave-uniform).  With PF the next
+// tile's inputs are fetched while the current one runs its LDS passes.
+template <class PL, int TB, int BPW, int SIDE, bool TGR, bool PF>
+__device__ __attribute__((noinline)) void ragged_chunk(const RaggedArgs &a, const RaggedItem &it, c32 *lds)
 {
     static_assert(TB * BPW == RT, "tile must fill the workgroup");
     static_assert(TB >= 64, "a wave must stay inside one block");
@@ -72,137 +74,172 @@ __device__ __attribute__((noinline)) void ragged_tile(const RaggedArgs &a, const
     constexpr bool FULLL = ITL * TB == NBL;
     constexpr uint32_t CB = 8, FB = 4;
     constexpr bool CONJ = SIDE == SIDE_OUT;
+    constexpr int OPT = OPT_SEQ_TWIDDLE;
     const float Nf = float(N);
 
     const int bi = threadIdx.x / TB;
     const int tid = threadIdx.x - bi * TB;
     c32 *L = lds + bi * N;
-    const bool valid = bi < it.count;
-    // wave-uniform block offsets
-    int blk = valid ? a.order[it.first + bi] : 0;
-    blk = __builtin_amdgcn_readfirstlane(blk);
-    const int64_t xo = a.x_off[blk];
-    const int64_t to = a.tap_off[blk];
-    const uint32_t nb = valid ? N : 0;          // empty resources for idle slots
-    const rsrc_t ri = make_rsrc(a.in + xo, nb * CB);
-    const rsrc_t ro = make_rsrc(a.out + xo, nb * CB);
-    const rsrc_t rt = make_rsrc(a.taps + to, nb * FB);
-    rsrc_t rx = ro, rg = ro;
-    if constexpr (TGR) {
-        rx = make_rsrc(a.aux + xo, nb * CB);
-        rg = make_rsrc(a.tapbar + xo, nb * FB);
-    }
+    const int ntiles = (it.count + BPW - 1) / BPW;
     bool zero_tap = false;
 
-    c32 w1s[TwSlots<PL, TB>::total()];
+    c32 w1s[TwSlots<PL, TB, OPT>::total()];
     if constexpr (NP > 1) {
         const c32 *tw = a.tw + a.tw_off[it.cls];
         static_for<1, NP>([&](auto pI) {
             constexpr int P = decltype(pI)::value;
             constexpr int NB = N / PL::get(P);
-            constexpr int IT = TwSlots<PL, TB>::it(P);
+            constexpr int IT = TwSlots<PL, TB, OPT>::it(P);
 #pragma unroll
             for (int i = 0; i < IT; ++i) {
                 const int j = tid + i * TB;
-                w1s[TwSlots<PL, TB>::off(P) + i] = (j < NB) ? tw[PL::tw_off(P) + j % PL::ns(P)] : c32{1.f, 0.f};
+                w1s[TwSlots<PL, TB, OPT>::off(P) + i] = (j < NB) ? tw[PL::tw_off(P) + j % PL::ns(P)] : c32{1.f, 0.f};
             }
         });
     }
 
-    // ---- pass 0: HBM -> registers -> filter -> DFT_R0
-    c32 v0[IT0][R0];
+    // wave-uniform resources of this thread's block in tile t (empty for idle slots)
+    struct Res {
+        rsrc_t in, out, taps, aux, tg;
+        bool valid;
+    };
+    auto res = [&](int t) {
+        Res r;
+        const int slot = t * BPW + bi;
+        r.valid = slot < it.count;
+        int blk = r.valid ? a.order[it.first + slot] : 0;
+        blk = __builtin_amdgcn_readfirstlane(blk);
+        const int64_t xo = a.x_off[blk];
+        const int64_t to = a.tap_off[blk];
+        const uint32_t nb = r.valid ? N : 0;
+        r.in = make_rsrc(a.in + xo, nb * CB);
+        r.out = make_rsrc(a.out + xo, nb * CB);
+        r.taps = make_rsrc(a.taps + to, nb * FB);
+        r.aux = r.out;
+        r.tg = r.out;
+        if constexpr (TGR) {
+            r.aux = make_rsrc(a.aux + xo, nb * CB);
+            r.tg = make_rsrc(a.tapbar + xo, nb * FB);
+        }
+        return r;
+    };
+
+    c32 x0[IT0][R0];
+    float t0[SIDE == SIDE_IN ? IT0 : 1][SIDE == SIDE_IN ? R0 : 1];
+    auto fetch = [&](const Res &r) {
 #pragma unroll
-    for (int i = 0; i < IT0; ++i) {
-        const int j = tid + i * TB;
-        if (FULL0 || j < NB0) {
-            static_for<0, R0>([&](auto rI) {
-                constexpr int r = decltype(rI)::value;
-                c32 x = ld_c(ri, j * CB, r * NB0 * CB);
-                if constexpr (SIDE == SIDE_IN) {
-                    const float t = ld_f(rt, j * FB, r * NB0 * FB);
-                    zero_tap |= valid && (t == 0.0f);
-                    x = scale(x, filter_factor(t, a.div, Nf));
-                } else {
-                    x = conj(x);
+        for (int i = 0; i < IT0; ++i) {
+            const int j = tid + i * TB;
+            if (FULL0 || j < NB0) {
+                static_for<0, R0>([&](auto rI) {
+                    constexpr int q = decltype(rI)::value;
+                    x0[i][q] = ld_c(r.in, j * CB, q * NB0 * CB);
+                    if constexpr (SIDE == SIDE_IN) t0[i][q] = ld_f(r.taps, j * FB, q * NB0 * FB);
+                });
+            }
+        }
+    };
+
+    Res cur = res(0);
+    if (PF) fetch(cur);
+    for (int t = 0; t < ntiles; ++t) {
+        if (!PF) fetch(cur);
+        // ---- pass 0: filter, DFT_R0
+        c32 v0[IT0][R0];
+#pragma unroll
+        for (int i = 0; i < IT0; ++i) {
+            const int j = tid + i * TB;
+            if (FULL0 || j < NB0) {
+                static_for<0, R0>([&](auto rI) {
+                    constexpr int q = decltype(rI)::value;
+                    if constexpr (SIDE == SIDE_IN) {
+                        zero_tap |= cur.valid && (t0[i][q] == 0.0f);
+                        v0[i][q] = scale(x0[i][q], filter_factor(t0[i][q], a.div, Nf));
+                    } else {
+                        v0[i][q] = conj(x0[i][q]);
+                    }
+                });
+                dft<R0>(v0[i]);
+            }
+        }
+        const Res next = res(t + 1 < ntiles ? t + 1 : t);
+        if constexpr (NP == 1) {
+#pragma unroll
+            for (int i = 0; i < IT0; ++i) {
+                const int j = tid + i * TB;
+                if (FULL0 || j < NB0) {
+                    static_for<0, R0>([&](auto rI) {
+                        constexpr int q = decltype(rI)::value;
+                        c32 w = CONJ ? conj(v0[i][q]) : v0[i][q];
+                        if constexpr (TGR) {
+                            const c32 sv = ld_c(cur.aux, j * CB, q * NB0 * CB);
+                            st_f(sv.x * w.x + sv.y * w.y, cur.tg, j * FB, q * NB0 * FB);
+                        }
+                        if constexpr (SIDE == SIDE_OUT) {
+                            const float tv = ld_f(cur.taps, j * FB, q * NB0 * FB);
+                            zero_tap |= cur.valid && (tv == 0.0f);
+                            w = scale(w, filter_factor(tv, a.div, Nf));
+                        }
+                        st_c(w, cur.out, j * CB, q * NB0 * CB);
+                    });
                 }
-                v0[i][r] = x;
-            });
-            dft<R0>(v0[i]);
-        }
-    }
-    if constexpr (NP == 1) {
+            }
+            if (PF && t + 1 < ntiles) fetch(next);
+        } else {
+            lds_barrier();   // the previous tile's last pass has finished reading LDS
 #pragma unroll
-        for (int i = 0; i < IT0; ++i) {
-            const int j = tid + i * TB;
-            if (FULL0 || j < NB0) {
-                static_for<0, R0>([&](auto rI) {
-                    constexpr int r = decltype(rI)::value;
-                    c32 w = CONJ ? conj(v0[i][r]) : v0[i][r];
-                    if constexpr (TGR) {
-                        const c32 s = ld_c(rx, j * CB, r * NB0 * CB);
-                        st_f(s.x * w.x + s.y * w.y, rg, j * FB, r * NB0 * FB);
-                    }
-                    if constexpr (SIDE == SIDE_OUT) {
-                        const float t = ld_f(rt, j * FB, r * NB0 * FB);
-                        zero_tap |= valid && (t == 0.0f);
-                        w = scale(w, filter_factor(t, a.div, Nf));
-                    }
-                    st_c(w, ro, j * CB, r * NB0 * CB);
-                });
+            for (int i = 0; i < IT0; ++i) {
+                const int j = tid + i * TB;
+                if (FULL0 || j < NB0) {
+                    static_for<0, R0>([&](auto rI) {
+                        constexpr int q = decltype(rI)::value;
+                        L[j * R0 + q] = v0[i][q];
+                    });
+                }
+            }
+            if (PF && t + 1 < ntiles) fetch(next);
+            // operands of the last pass, fetched while the LDS passes run
+            float tl[SIDE == SIDE_OUT ? ITL : 1][SIDE == SIDE_OUT ? RL : 1];
+            c32 sl[TGR ? ITL : 1][TGR ? RL : 1];
+#pragma unroll
+            for (int i = 0; i < ITL; ++i) {
+                const int j = tid + i * TB;
+                if (FULLL || j < NBL) {
+                    static_for<0, RL>([&](auto rI) {
+                        constexpr int q = decltype(rI)::value;
+                        if constexpr (SIDE == SIDE_OUT) tl[i][q] = ld_f(cur.taps, j * FB, q * NSL * FB);
+                        if constexpr (TGR) sl[i][q] = ld_c(cur.aux, j * CB, q * NSL * CB);
+                    });
+                }
+            }
+            lds_barrier();
+            lds_passes<PL, TB, 1, OPT>(L, tid, w1s);
+            constexpr int SLOTL = TwSlots<PL, TB, OPT>::off(NP - 1);
+#pragma unroll
+            for (int i = 0; i < ITL; ++i) {
+                const int j = tid + i * TB;
+                if (FULLL || j < NBL) {
+                    c32 v[RL];
+                    static_for<0, RL>([&](auto rI) {
+                        constexpr int q = decltype(rI)::value;
+                        v[q] = L[j + q * NBL];
+                    });
+                    twiddle<OPT, RL>(v, w1s[SLOTL + i]);
+                    dft<RL>(v);
+                    static_for<0, RL>([&](auto rI) {
+                        constexpr int q = decltype(rI)::value;
+                        c32 w = CONJ ? conj(v[q]) : v[q];
+                        if constexpr (TGR) st_f(sl[i][q].x * w.x + sl[i][q].y * w.y, cur.tg, j * FB, q * NSL * FB);
+                        if constexpr (SIDE == SIDE_OUT) {
+                            zero_tap |= cur.valid && (tl[i][q] == 0.0f);
+                            w = scale(w, filter_factor(tl[i][q], a.div, Nf));
+                        }
+                        st_c(w, cur.out, j * CB, q * NSL * CB);
+                    });
+                }
             }
         }
-    } else {
-        lds_barrier();   // the previous item's last pass has finished reading LDS
-#pragma unroll
-        for (int i = 0; i < IT0; ++i) {
-            const int j = tid + i * TB;
-            if (FULL0 || j < NB0) {
-                static_for<0, R0>([&](auto rI) {
-                    constexpr int r = decltype(rI)::value;
-                    L[j * R0 + r] = v0[i][r];
-                });
-            }
-        }
-        // operands of the last pass, fetched while the LDS passes run
-        float tl[SIDE == SIDE_OUT ? ITL : 1][SIDE == SIDE_OUT ? RL : 1];
-        c32 sl[TGR ? ITL : 1][TGR ? RL : 1];
-#pragma unroll
-        for (int i = 0; i < ITL; ++i) {
-            const int j = tid + i * TB;
-            if (FULLL || j < NBL) {
-                static_for<0, RL>([&](auto rI) {
-                    constexpr int r = decltype(rI)::value;
-                    if constexpr (SIDE == SIDE_OUT) tl[i][r] = ld_f(rt, j * FB, r * NSL * FB);
-                    if constexpr (TGR) sl[i][r] = ld_c(rx, j * CB, r * NSL * CB);
-                });
-            }
-        }
-        lds_barrier();
-        lds_passes<PL, TB, 1, OPT_SEQ_TWIDDLE>(L, tid, w1s);
-        constexpr int SLOTL = TwSlots<PL, TB>::off(NP - 1);
-#pragma unroll
-        for (int i = 0; i < ITL; ++i) {
-            const int j = tid + i * TB;
-            if (FULLL || j < NBL) {
-                c32 v[RL];
-                static_for<0, RL>([&](auto rI) {
-                    constexpr int r = decltype(rI)::value;
-                    v[r] = L[j + r * NBL];
-                });
-                twiddle<OPT_SEQ_TWIDDLE, RL>(v, w1s[SLOTL + i]);
-                dft<RL>(v);
-                static_for<0, RL>([&](auto rI) {
-                    constexpr int r = decltype(rI)::value;
-                    c32 w = CONJ ? conj(v[r]) : v[r];
-                    if constexpr (TGR) st_f(sl[i][r].x * w.x + sl[i][r].y * w.y, rg, j * FB, r * NSL * FB);
-                    if constexpr (SIDE == SIDE_OUT) {
-                        zero_tap |= valid && (tl[i][r] == 0.0f);
-                        w = scale(w, filter_factor(tl[i][r], a.div, Nf));
-                    }
-                    st_c(w, ro, j * CB, r * NSL * CB);
-                });
-            }
-        }
+        cur = next;
     }
     if (zero_tap && a.div && a.status) *a.status = 1;
 }
@@ -220,6 +257,9 @@ struct RClass {
     static constexpr int TB0 = pow2_floor(PL::max_nb());
     static constexpr int TB = TB0 < 64 ? 64 : (TB0 > RT ? RT : TB0);
     static constexpr int BPW = RT / TB;
+    // prefetching costs a second copy of the pass-0 operands in registers;
+    // the largest blocks cannot afford it
+    static constexpr bool PF = PL::total() <= 8192;
     static constexpr int lds() { return PL::count > 1 ? BPW * PL::total() * 8 : 0; }
 };
 
@@ -270,7 +310,7 @@ __global__ void __launch_bounds__(RT) ragged_kernel(RaggedArgs a)
 #define BT_CLASS_CASE(K_, M_)                                                                      \
     if (it.cls == cls) {                                                                           \
         using C = RClass<K_, M_>;                                                                  \
-        ragged_tile<typename C::PL, C::TB, C::BPW, SIDE, TGR>(a, it, lds_dyn);                     \
+        ragged_chunk<typename C::PL, C::TB, C::BPW, SIDE, TGR, C::PF>(a, it, lds_dyn);             \
     }                                                                                              \
     ++cls;
         BT_RAGGED_CLASSES(BT_CLASS_CASE)
@@ -356,6 +396,15 @@ extern "C" int transform_ragged_plan_create(const int32_t *K, const int32_t *M, 
                                             const int64_t *tap_off, int64_t nblocks,
                                             int64_t total_points, tf_ragged_plan *plan)
 {
+    return transform_ragged_plan_create_ex(K, M, x_off, tap_off, nblocks, total_points, 0, plan);
+}
+
+extern "C" int transform_ragged_plan_create_ex(const int32_t *K, const int32_t *M, const int64_t *x_off,
+                                               const int64_t *tap_off, int64_t nblocks,
+                                               int64_t total_points, int32_t chunk_tiles,
+                                               tf_ragged_plan *plan)
+{
+    if (chunk_tiles < 0) return TF_EINVAL;
     if (!plan) return TF_EINVAL;
     *plan = nullptr;
     if (nblocks < 0 || total_points < 0 || (nblocks > 0 && (!K || !M || !x_off || !tap_off)))
@@ -375,19 +424,34 @@ extern "C" int transform_ragged_plan_create(const int32_t *K, const int32_t *M, 
         if (x_off[b] < 0 || x_off[b] + N > total_points || tap_off[b] < 0) return TF_EINVAL;
         members[f->second].push_back(int(b));
     }
-    // tiles of same-class blocks, sorted by cost (largest first)
-    std::vector<int> order;
-    std::vector<RaggedItem> items;
-    std::vector<double> cost;
+    // chunks of `chunk_tiles` tiles of same-class blocks, sorted by cost (largest
+    // first); 0 picks about eight chunks per resident workgroup
+    int64_t tiles = 0;
     int max_lds = 0;
     for (int c = 0; c < ncls; ++c) {
         if (members[c].empty()) continue;
+        tiles += (int64_t(members[c].size()) + cls[c].BPW - 1) / cls[c].BPW;
         max_lds = std::max(max_lds, cls[c].lds);
-        for (size_t s = 0; s < members[c].size(); s += cls[c].BPW) {
+    }
+    int dev_cus = 0;
+    {
+        int d = 0;
+        if (hipGetDevice(&d) != hipSuccess ||
+            hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, d) != hipSuccess)
+            dev_cus = 256;
+    }
+    if (chunk_tiles == 0) chunk_tiles = int(std::max<int64_t>(1, tiles / (8 * int64_t(dev_cus))));
+    std::vector<int> order;
+    std::vector<RaggedItem> items;
+    std::vector<double> cost;
+    for (int c = 0; c < ncls; ++c) {
+        if (members[c].empty()) continue;
+        const size_t per_chunk = size_t(cls[c].BPW) * chunk_tiles;
+        for (size_t s = 0; s < members[c].size(); s += per_chunk) {
             RaggedItem it{};
             it.cls = c;
             it.first = int(order.size());
-            it.count = int(std::min<size_t>(cls[c].BPW, members[c].size() - s));
+            it.count = int(std::min<size_t>(per_chunk, members[c].size() - s));
             for (int q = 0; q < it.count; ++q) order.push_back(members[c][s + q]);
             items.push_back(it);
             cost.push_back(double(it.count) * cls[c].N * std::log2(double(cls[c].N)));

@@ -22,14 +22,26 @@ import torch
 from . import _native as nat
 
 
+_RAGGED_CHUNK = 0      # tiles per ragged work item (0: automatic)
+
+
 def load_schedules(path: Optional[str] = None) -> bool:
     """Apply autotuned schedule choices from a JSON file ($BT_SCHEDULES, or
-    schedules.json next to this module).  Returns True when a file was applied."""
+    schedules.json next to this module): per-(K, M) schedules go to the library,
+    the ragged work-item size ("ragged_chunk_tiles") to RaggedPlan.  Returns True
+    when a file was applied."""
+    import json
     import os
+    global _RAGGED_CHUNK
     path = path or os.environ.get("BT_SCHEDULES") or os.path.join(
         os.path.dirname(os.path.abspath(__file__)), "schedules.json")
     if not os.path.exists(path):
         return False
+    try:
+        with open(path) as f:
+            _RAGGED_CHUNK = int(json.load(f).get("ragged_chunk_tiles", 0))
+    except (OSError, ValueError, TypeError):
+        _RAGGED_CHUNK = 0
     return nat.load().transform_load_schedule(path.encode()) == nat.TF_OK
 
 
@@ -293,7 +305,7 @@ class RaggedPlan:
 
     DIRECTIONS = {"forward": 0, "inverse": 1, "adjoint": 2}
 
-    def __init__(self, K, M, x_off, tap_off, total_points: int):
+    def __init__(self, K, M, x_off, tap_off, total_points: int, chunk_tiles: Optional[int] = None):
         import numpy as np
         K = np.ascontiguousarray(K, dtype=np.int32)
         M = np.ascontiguousarray(M, dtype=np.int32)
@@ -304,11 +316,13 @@ class RaggedPlan:
         self.total_points = int(total_points)
         self.nblocks = int(K.size)
         self._lib = nat.load()
+        if chunk_tiles is None:
+            chunk_tiles = _RAGGED_CHUNK
         h = ctypes.c_void_p()
-        nat.check("transform_ragged_plan_create", self._lib.transform_ragged_plan_create(
+        nat.check("transform_ragged_plan_create", self._lib.transform_ragged_plan_create_ex(
             K.ctypes.data_as(ctypes.c_void_p), M.ctypes.data_as(ctypes.c_void_p),
             xo.ctypes.data_as(ctypes.c_void_p), to.ctypes.data_as(ctypes.c_void_p),
-            self.nblocks, self.total_points, ctypes.byref(h)))
+            self.nblocks, self.total_points, int(chunk_tiles), ctypes.byref(h)))
         self._h = h
 
     def close(self):
