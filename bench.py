@@ -320,6 +320,32 @@ def extras(T, W, args):
     res["precision"] = prec
     del S, taps, yb, y, sb
 
+    # ---- decimated eq. (7) operator on the standard GPU workload's shape
+    cfg = W.CONFIGS["plain_gpu"]
+    K, M, B = cfg.K, cfg.M, cfg.nblocks
+    N = K * M
+    S_h, taps_h = W.make_uniform(cfg)
+    S = torch.from_numpy(S_h).to(dev)
+    taps = torch.from_numpy(taps_h).to(dev)
+    d = torch.empty((B, K), dtype=torch.complex64, device=dev)
+    db = torch.from_numpy(W.cn01(np.random.default_rng(10), (B, K)).astype(np.complex64)).to(dev)
+    sb = torch.empty_like(S)
+
+    def decstep(i):
+        T.transform_decimated(S, taps, K, M, out=d)
+        T.transform_decimated_adjoint(db, taps, K, M, out=sb)
+
+    t = _timeit(decstep, steps)
+    byts = (16.0 * N + 16.0 * K) * B
+    idx = np.array([0, 2048, 4095])
+    T.transform_decimated(S, taps, K, M, out=d)
+    res["decimated"] = {"blocks_per_s": round(B / t, 1), "ms_per_step": round(t * 1e3, 4),
+                        "achieved_GBps": round(byts / t / 1e9, 1),
+                        "frac_hbm_peak": round(byts / t / 1e9 / HBM_PEAK_GBS, 4),
+                        "rel_l2_forward": _rel(d.cpu().numpy()[idx], O.decimated(S_h[idx], taps_h, K)),
+                        "workload": "eq. (7) on 4096 blocks K=128 M=15: forward (N -> K) + adjoint (K -> N)"}
+    del S, taps, d, db, sb
+
     # ---- differentiation workload: forward + adjoint with the shared tap gradient
     cfg = W.CONFIGS["differentiation"]
     K, M, B = cfg.K, cfg.M, cfg.nblocks

@@ -136,6 +136,28 @@ int transform_inverse_adjoint(const void *coeffs_bar, const float *taps, const v
                               int32_t compute, void *workspace, size_t workspace_bytes,
                               void *stream);
 
+/*
+ * transform_decimated -- eq. (7): the polynomial of eq. (6) read at the K regular
+ * points q/K only (filter, circular fold of the N = K M spectrum onto K bins,
+ * K-point IDFT):  out_q = sum_{n<N} Lambda_n S_n e^{+j 2 pi n q / K},  q < K.
+ *   coeffs  in : S, complex64 [nblocks][N]
+ *   taps    in : float32 [N] (tap_stride 0) or [nblocks][N] (tap_stride N)
+ *   samples out: complex64 [nblocks][K]
+ * K a power of two in [16, 1024], M in [1, 4096].
+ */
+int transform_decimated(const void *coeffs, const float *taps, void *samples, int64_t nblocks,
+                        int32_t K, int32_t M, int64_t tap_stride, void *stream);
+
+/*
+ * transform_decimated_adjoint -- Hermitian of transform_decimated:
+ *   Sbar_n = Lambda_n sum_{q<K} ybar_q e^{-j 2 pi n q / K},  n < N.
+ *   samples_bar in : complex64 [nblocks][K]
+ *   coeffs_bar  out: complex64 [nblocks][N]
+ */
+int transform_decimated_adjoint(const void *samples_bar, const float *taps, void *coeffs_bar,
+                                int64_t nblocks, int32_t K, int32_t M, int64_t tap_stride,
+                                void *stream);
+
 /* Bytes of device workspace a call with these arguments needs (0 when none).
    `with_tapbar` is 1 when the call computes taps_bar. */
 size_t transform_workspace_size(int64_t nblocks, int32_t K, int32_t M, int64_t tap_stride,

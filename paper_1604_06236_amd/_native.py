@@ -34,7 +34,7 @@ EXPORTED = (
     "transform_schedule_selected",
     "transform_load_schedule", "transform_save_schedule",
     "transform_ragged_plan_create", "transform_ragged_plan_create_ex", "transform_ragged_plan_destroy",
-    "transform_ragged_execute",
+    "transform_ragged_execute", "transform_decimated", "transform_decimated_adjoint",
 )
 
 _lib = None
@@ -63,6 +63,8 @@ def load() -> ctypes.CDLL:
     lib.transform_inverse.argtypes = [vp, vp, vp, i64, i32, i32, i64, i32, vp, vp, sz, vp]
     lib.transform_adjoint.argtypes = [vp, vp, vp, vp, vp, i64, i32, i32, i64, i32, vp, sz, vp]
     lib.transform_inverse_adjoint.argtypes = [vp, vp, vp, vp, vp, i64, i32, i32, i64, i32, vp, sz, vp]
+    lib.transform_decimated.argtypes = [vp, vp, vp, i64, i32, i32, i64, vp]
+    lib.transform_decimated_adjoint.argtypes = [vp, vp, vp, i64, i32, i32, i64, vp]
     lib.transform_workspace_size.argtypes = [i64, i32, i32, i64, i32, i32]
     lib.transform_workspace_size.restype = sz
     lib.transform_prepare.argtypes = [i32, i32, i32]

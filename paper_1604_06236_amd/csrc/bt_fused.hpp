@@ -272,16 +272,17 @@ __device__ __forceinline__ float filter_factor(float t, int div, float Nf)
 }
 
 // ------------------------------------------------------------------ LDS passes
-template <class PL, int TB, int P, int OPT = 0>
+// passes P <= p < END (default: all but the last) in place in LDS
+template <class PL, int TB, int P, int OPT = 0, int END = PL::count - 1>
 __device__ __forceinline__ void lds_passes(c32 *L, int tid, const c32 *w1s)
 {
-    if constexpr (P < PL::count - 1) {
+    if constexpr (P < END) {
         constexpr int N = PL::total();
         constexpr int R = PL::get(P);
         constexpr int NS = PL::ns(P);
         constexpr int NB = N / R;
         constexpr int IT = (NB + TB - 1) / TB;
-        constexpr int SLOT = TwSlots<PL, TB, OPT>::off(P);
+        constexpr int SLOT = P == 0 ? 0 : TwSlots<PL, TB, OPT>::off(P);
         c32 v[IT][R];
 #pragma unroll
         for (int i = 0; i < IT; ++i) {
@@ -291,7 +292,7 @@ __device__ __forceinline__ void lds_passes(c32 *L, int tid, const c32 *w1s)
                     constexpr int r = decltype(rI)::value;
                     v[i][r] = L[j + r * NB];
                 });
-                twiddle<OPT, R>(v[i], w1s[SLOT + i]);
+                if constexpr (NS > 1) twiddle<OPT, R>(v[i], w1s[SLOT + i]);
                 dft<R>(v[i]);
             }
         }
@@ -309,7 +310,7 @@ __device__ __forceinline__ void lds_passes(c32 *L, int tid, const c32 *w1s)
             }
         }
         lds_barrier();
-        lds_passes<PL, TB, P + 1, OPT>(L, tid, w1s);
+        lds_passes<PL, TB, P + 1, OPT, END>(L, tid, w1s);
     }
 }
 

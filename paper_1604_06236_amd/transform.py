@@ -51,7 +51,7 @@ __all__ = [
     "transform_forward", "transform_inverse", "transform_adjoint", "transform_inverse_adjoint",
     "transform_prepare", "workspace_size", "schedules", "select_schedule", "Transform",
     "InverseTransform", "forward", "inverse", "RaggedPlan", "bind_forward", "bind_adjoint",
-    "selected_schedule",
+    "selected_schedule", "transform_decimated", "transform_decimated_adjoint",
 ]
 
 
@@ -177,6 +177,36 @@ def transform_inverse_adjoint(coeffs_bar: torch.Tensor, taps: torch.Tensor, K: i
         _ptr(coeffs_bar), _ptr(taps), _ptr(coeffs), _ptr(out), _ptr(tb), B, K, M, ts,
         _compute(compute), _ptr(ws), wsb, _stream(coeffs_bar.device)))
     return out, tb
+
+
+# ------------------------------------------------------------------ decimated operator (eq. (7))
+def transform_decimated(coeffs: torch.Tensor, taps: torch.Tensor, K: int, M: int, *,
+                        out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """out[b, q] = sum_n taps_n S[b, n] e^{+j 2 pi n q / K}, q < K (eq. (7))."""
+    B = _check_blocks(coeffs, "coeffs", K, M)
+    ts = _tap_stride(taps, B, K * M, coeffs.device)
+    out = torch.empty((B, K), dtype=torch.complex64, device=coeffs.device) if out is None else out
+    if out.shape != (B, K) or out.dtype != torch.complex64 or not out.is_contiguous():
+        raise ValueError(f"out must be contiguous complex64 [{B}, {K}]")
+    nat.check("transform_decimated", nat.load().transform_decimated(
+        _ptr(coeffs), _ptr(taps), _ptr(out), B, K, M, ts, _stream(coeffs.device)))
+    return out
+
+
+def transform_decimated_adjoint(samples_bar: torch.Tensor, taps: torch.Tensor, K: int, M: int, *,
+                                out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Sbar[b, n] = taps_n sum_q ybar[b, q] e^{-j 2 pi n q / K}."""
+    if samples_bar.dtype != torch.complex64 or samples_bar.dim() != 2 or samples_bar.shape[1] != K \
+            or not samples_bar.is_contiguous():
+        raise ValueError(f"samples_bar must be contiguous complex64 [B, {K}]")
+    B = samples_bar.shape[0]
+    N = K * M
+    ts = _tap_stride(taps, B, N, samples_bar.device)
+    out = torch.empty((B, N), dtype=torch.complex64, device=samples_bar.device) if out is None else out
+    _check_blocks(out, "coeffs_bar", K, M)
+    nat.check("transform_decimated_adjoint", nat.load().transform_decimated_adjoint(
+        _ptr(samples_bar), _ptr(taps), _ptr(out), B, K, M, ts, _stream(samples_bar.device)))
+    return out
 
 
 # ------------------------------------------------------------------ pre-marshalled calls
