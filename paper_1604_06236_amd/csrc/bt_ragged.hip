@@ -57,7 +57,7 @@ struct RaggedArgs {
 // straddles two blocks and block bases are wave-uniform).  With PF the next
 // tile's inputs are fetched while the current one runs its LDS passes.
 template <class PL, int TB, int BPW, int SIDE, bool TGR, bool PF>
-__device__ __attribute__((noinline)) void ragged_chunk(const RaggedArgs &a, const RaggedItem &it, c32 *lds)
+__device__ __forceinline__ void ragged_chunk(const RaggedArgs &a, const RaggedItem &it, c32 *lds)
 {
     static_assert(TB * BPW == RT, "tile must fill the workgroup");
     static_assert(TB >= 64, "a wave must stay inside one block");
@@ -77,8 +77,13 @@ __device__ __attribute__((noinline)) void ragged_chunk(const RaggedArgs &a, cons
     constexpr int OPT = OPT_SEQ_TWIDDLE;
     const float Nf = float(N);
 
-    const int bi = threadIdx.x / TB;
-    const int tid = threadIdx.x - bi * TB;
+    // the thread index goes through an opaque move so that the per-class
+    // values derived from it are computed here, not hoisted out of the queue
+    // loop where every class's copies would stay live at once
+    int tx = threadIdx.x;
+    asm volatile("" : "+v"(tx));
+    const int bi = tx / TB;
+    const int tid = tx - bi * TB;
     c32 *L = lds + bi * N;
     const int ntiles = (it.count + BPW - 1) / BPW;
     bool zero_tap = false;
@@ -249,17 +254,53 @@ __device__ __attribute__((noinline)) void ragged_chunk(const RaggedArgs &a, cons
 // most 16 keep the shared register allocation (the maximum over classes) low
 template <int K> struct RKPlan { using type = typename KPlan<K>::type; };
 template <> struct RKPlan<512> { using type = Radices<8, 8, 8>; };
-template <> struct RKPlan<1024> { using type = Radices<16, 16, 4>; };
+template <> struct RKPlan<1024> { using type = Radices<8, 8, 16>; };
+
+// Per-class fitting inside the 128-VGPR budget of a 1024-thread workgroup.
+// CEIL rounds the threads per block up to the next power of two above the
+// widest pass (fewer elements per thread); the PF_* flags say whether the
+// forward / tap-gradient adjoint / plain adjoint prefetch the next tile (a
+// second copy of the pass-0 operands in registers).  The defaults fit most
+// classes; the specialisations below are the classes whose compiled code
+// otherwise spills (values read from the compiler's per-kernel VGPR and spill
+// counts).
+template <int K, int M> struct RTune {
+    static constexpr bool CEIL = false;
+    static constexpr bool PF_FWD = true, PF_TG = true, PF_ADJ = true;
+};
+#define BT_RTUNE(K_, M_, CEIL_, FWD_, TG_, ADJ_)                         \
+    template <> struct RTune<K_, M_> {                                    \
+        static constexpr bool CEIL = CEIL_;                               \
+        static constexpr bool PF_FWD = FWD_, PF_TG = TG_, PF_ADJ = ADJ_;  \
+    };
+BT_RTUNE(64, 9, true, true, true, true)
+BT_RTUNE(64, 15, true, true, false, true)
+BT_RTUNE(128, 9, false, true, false, true)
+BT_RTUNE(128, 15, false, false, false, true)
+BT_RTUNE(256, 3, false, true, false, true)
+BT_RTUNE(256, 5, false, true, false, true)
+BT_RTUNE(256, 7, false, true, false, true)
+BT_RTUNE(256, 9, false, true, false, true)
+BT_RTUNE(256, 15, false, false, false, true)
+BT_RTUNE(512, 9, true, true, true, true)
+BT_RTUNE(512, 15, true, true, false, true)
+BT_RTUNE(1024, 7, false, true, false, true)
+BT_RTUNE(1024, 9, false, true, false, true)
+BT_RTUNE(1024, 15, false, false, false, false)
+#undef BT_RTUNE
 
 template <int K, int M>
 struct RClass {
     using PL = typename PrependM<M, typename RKPlan<K>::type>::type;
-    static constexpr int TB0 = pow2_floor(PL::max_nb());
+    using Tune = RTune<K, M>;
+    static constexpr int TB0 = Tune::CEIL ? 2 * pow2_floor(PL::max_nb() - 1) : pow2_floor(PL::max_nb());
     static constexpr int TB = TB0 < 64 ? 64 : (TB0 > RT ? RT : TB0);
     static constexpr int BPW = RT / TB;
-    // prefetching costs a second copy of the pass-0 operands in registers;
-    // the largest blocks cannot afford it
-    static constexpr bool PF = PL::total() <= 8192;
+    template <int SIDE, bool TGR>
+    static constexpr bool pf()
+    {
+        return SIDE == SIDE_IN ? Tune::PF_FWD : (TGR ? Tune::PF_TG : Tune::PF_ADJ);
+    }
     static constexpr int lds() { return PL::count > 1 ? BPW * PL::total() * 8 : 0; }
 };
 
@@ -310,7 +351,7 @@ __global__ void __launch_bounds__(RT) ragged_kernel(RaggedArgs a)
 #define BT_CLASS_CASE(K_, M_)                                                                      \
     if (it.cls == cls) {                                                                           \
         using C = RClass<K_, M_>;                                                                  \
-        ragged_chunk<typename C::PL, C::TB, C::BPW, SIDE, TGR, C::PF>(a, it, lds_dyn);             \
+        ragged_chunk<typename C::PL, C::TB, C::BPW, SIDE, TGR, C::template pf<SIDE, TGR>()>(a, it, lds_dyn);           \
     }                                                                                              \
     ++cls;
         BT_RAGGED_CLASSES(BT_CLASS_CASE)

@@ -21,7 +21,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--what", default="forward",
                     choices=["forward", "adjoint", "forward_adjoint", "ragged", "split_bf16",
-                             "split_fp16", "differentiation"])
+                             "split_fp16", "differentiation", "decimated", "all"])
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--copy-mib", type=int, default=256)
     args = ap.parse_args()
@@ -40,33 +40,61 @@ def main():
     torch.cuda.synchronize()
     del a, b
 
-    if args.what == "ragged":
+    if args.what == "all":
+        for w in ("forward_adjoint", "ragged", "split_bf16", "split_fp16", "differentiation", "decimated"):
+            run(w, args.reps, T, W, np, torch)
+        return
+    run(args.what, args.reps, T, W, np, torch)
+
+
+def run(what, reps, T, W, np, torch):
+    dev = "cuda"
+    if what == "decimated":
+        c = W.CONFIGS["plain_gpu"]
+        S_h, taps_h = W.make_uniform(c)
+        S = torch.from_numpy(S_h).to(dev)
+        taps = torch.from_numpy(taps_h).to(dev)
+        d = torch.empty((c.nblocks, c.K), dtype=torch.complex64, device=dev)
+        sb = torch.empty_like(S)
+        for _ in range(reps):
+            T.transform_decimated(S, taps, c.K, c.M, out=d)
+            T.transform_decimated_adjoint(d, taps, c.K, c.M, out=sb)
+        torch.cuda.synchronize()
+        print(f"decimated: {reps} forward+adjoint on plain_gpu", flush=True)
+        return
+    if what == "ragged":
         lay, S_h, taps_h = W.make_ragged("ragged")
         plan = T.RaggedPlan(lay.K, lay.M, lay.x_off, lay.tap_off, lay.total)
         S = torch.from_numpy(S_h).to(dev)
         taps = torch.from_numpy(taps_h).to(dev)
-        for _ in range(args.reps):
-            y = plan.execute("forward", S, taps, use_graph=False)
+        y = torch.empty_like(S)
+        sb = torch.empty_like(S)
+        for _ in range(reps):
+            plan.execute("forward", S, taps, out=y, use_graph=False)
+            plan.execute("adjoint", y, taps, out=sb, use_graph=False)
+            plan.execute("adjoint", y, taps, out=sb, aux=S, want_taps_bar=True, use_graph=False)
         torch.cuda.synchronize()
-        print(f"ragged: {args.reps} forward launches over {lay.K.size} blocks", flush=True)
+        plan.close()
+        print(f"ragged: {reps} x (forward, adjoint, adjoint with tap gradient) over {lay.K.size} blocks",
+              flush=True)
         return
     cfg = {"split_bf16": "precision", "split_fp16": "precision",
-           "differentiation": "differentiation"}.get(args.what, "plain_gpu")
+           "differentiation": "differentiation"}.get(what, "plain_gpu")
     c = W.CONFIGS[cfg]
     S_h, taps_h = W.make_uniform(c)
     S = torch.from_numpy(S_h).to(dev)
     taps = torch.from_numpy(taps_h).to(dev)
     y = torch.empty_like(S)
-    compute = args.what if args.what.startswith("split") else "fp32"
-    for _ in range(args.reps):
-        if args.what in ("forward", "forward_adjoint", "split_bf16", "split_fp16", "differentiation"):
+    compute = what if what.startswith("split") else "fp32"
+    for _ in range(reps):
+        if what in ("forward", "forward_adjoint", "split_bf16", "split_fp16", "differentiation"):
             T.transform_forward(S, taps, c.K, c.M, out=y, compute=compute)
-        if args.what in ("adjoint", "forward_adjoint"):
+        if what in ("adjoint", "forward_adjoint"):
             T.transform_adjoint(S, taps, c.K, c.M, out=y)
-        if args.what == "differentiation":
+        if what == "differentiation":
             T.transform_adjoint(y, taps, c.K, c.M, coeffs=S, want_taps_bar=True)
     torch.cuda.synchronize()
-    print(f"{args.what}: {args.reps} reps on {cfg} ({c.nblocks} blocks, K={c.K}, M={c.M})", flush=True)
+    print(f"{what}: {reps} reps on {cfg} ({c.nblocks} blocks, K={c.K}, M={c.M})", flush=True)
 
 
 if __name__ == "__main__":
