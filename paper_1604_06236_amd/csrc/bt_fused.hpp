@@ -271,6 +271,26 @@ __device__ __forceinline__ float filter_factor(float t, int div, float Nf)
     return div ? r : t;
 }
 
+// filter factors of a register array of taps, in place: the division (inverse
+// side) is a wave-uniform branch on `div`, so the multiplying directions skip
+// the reciprocal and the zero-tap test altogether.  `row(i)` says whether row i
+// holds loaded taps (rows past the butterfly count are never loaded).
+template <int A, int B, class Row>
+__device__ __forceinline__ void tap_factors(float (&t)[A][B], int div, float Nf, bool &zero_tap, Row row)
+{
+    if (div) {
+#pragma unroll
+        for (int i = 0; i < A; ++i) {
+            const bool ok = row(i);
+#pragma unroll
+            for (int r = 0; r < B; ++r) {
+                zero_tap |= ok && (t[i][r] == 0.0f);
+                t[i][r] = __builtin_amdgcn_rcpf(Nf * t[i][r]);
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ LDS passes
 // passes P <= p < END (default: all but the last) in place in LDS
 template <class PL, int TB, int P, int OPT = 0, int END = PL::count - 1>
@@ -484,6 +504,9 @@ __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
             if (PREFETCH && g + gridDim.x < ngroups) fetch(g + gridDim.x);
         } else {
             // ---- pass 0 on the fetched operands: filter, length-R0 DFT (no twiddle, Ns = 1)
+            if constexpr (SIDE == SIDE_IN && TG != TG_IN_)
+                tap_factors(t0, a.div, Nf, zero_tap,
+                            [&](int i) { return FULL0 || MP::template j<0>(tid, i) < NB0; });
             c32 v0[IT0][R0];
 #pragma unroll
             for (int i = 0; i < IT0; ++i) {
@@ -496,10 +519,10 @@ __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
                             const float tg = -(x0[i][r].x * s.x + x0[i][r].y * s.y) / t0[i][r];
                             if (shared_taps) acc[i * R0 + r] += tg;
                             else st_f(tg, rg, (boff + j) * FB, r * NB0 * FB);
-                        }
-                        if constexpr (SIDE == SIDE_IN) {
                             zero_tap |= (t0[i][r] == 0.0f);
                             v0[i][r] = scale(x0[i][r], filter_factor(t0[i][r], a.div, Nf));
+                        } else if constexpr (SIDE == SIDE_IN) {
+                            v0[i][r] = scale(x0[i][r], t0[i][r]);
                         } else {
                             v0[i][r] = conj(x0[i][r]);
                         }
@@ -540,6 +563,9 @@ __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
             lds_passes<PL, TB, 1, OPT>(L, tid, w1s);
 
             // ---- last pass: LDS -> registers -> twiddle -> DFT_RL -> HBM
+            if constexpr (SIDE == SIDE_OUT)
+                tap_factors(tl, a.div, Nf, zero_tap,
+                            [&](int i) { return FULLL || MP::template j<NP - 1>(tid, i) < NBL; });
             constexpr int SLOTL = TwSlots<PL, TB, OPT>::off(NP - 1);
             constexpr int STEP = PAIRL ? 2 : 1;
 #pragma unroll
@@ -567,10 +593,7 @@ __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
                                 if (shared_taps) acc[(i + h) * RL + r] += tg;
                                 else st_f(tg, rg, (boff + j + h) * FB, r * NSL * FB);
                             }
-                            if constexpr (SIDE == SIDE_OUT) {
-                                zero_tap |= (tl[i + h][r] == 0.0f);
-                                w[h] = scale(w[h], filter_factor(tl[i + h][r], a.div, Nf));
-                            }
+                            if constexpr (SIDE == SIDE_OUT) w[h] = scale(w[h], tl[i + h][r]);
                         }
                         if constexpr (PAIRL) st_c2<NTA>(w[0], w[1], ro, (boff + j) * CB, r * NSL * CB);
                         else st_c<NTA>(w[0], ro, (boff + j) * CB, r * NSL * CB);

@@ -150,6 +150,9 @@ __device__ __forceinline__ void ragged_chunk(const RaggedArgs &a, const RaggedIt
     for (int t = 0; t < ntiles; ++t) {
         if (!PF) fetch(cur);
         // ---- pass 0: filter, DFT_R0
+        if constexpr (SIDE == SIDE_IN && NP > 1)
+            tap_factors(t0, a.div, Nf, zero_tap,
+                        [&](int i) { return cur.valid && (FULL0 || tid + i * TB < NB0); });
         c32 v0[IT0][R0];
 #pragma unroll
         for (int i = 0; i < IT0; ++i) {
@@ -157,7 +160,9 @@ __device__ __forceinline__ void ragged_chunk(const RaggedArgs &a, const RaggedIt
             if (FULL0 || j < NB0) {
                 static_for<0, R0>([&](auto rI) {
                     constexpr int q = decltype(rI)::value;
-                    if constexpr (SIDE == SIDE_IN) {
+                    if constexpr (SIDE == SIDE_IN && NP > 1) {
+                        v0[i][q] = scale(x0[i][q], t0[i][q]);
+                    } else if constexpr (SIDE == SIDE_IN) {
                         zero_tap |= cur.valid && (t0[i][q] == 0.0f);
                         v0[i][q] = scale(x0[i][q], filter_factor(t0[i][q], a.div, Nf));
                     } else {
@@ -219,6 +224,9 @@ __device__ __forceinline__ void ragged_chunk(const RaggedArgs &a, const RaggedIt
             }
             lds_barrier();
             lds_passes<PL, TB, 1, OPT>(L, tid, w1s);
+            if constexpr (SIDE == SIDE_OUT)
+                tap_factors(tl, a.div, Nf, zero_tap,
+                            [&](int i) { return cur.valid && (FULLL || tid + i * TB < NBL); });
             constexpr int SLOTL = TwSlots<PL, TB, OPT>::off(NP - 1);
 #pragma unroll
             for (int i = 0; i < ITL; ++i) {
@@ -235,10 +243,7 @@ __device__ __forceinline__ void ragged_chunk(const RaggedArgs &a, const RaggedIt
                         constexpr int q = decltype(rI)::value;
                         c32 w = CONJ ? conj(v[q]) : v[q];
                         if constexpr (TGR) st_f(sl[i][q].x * w.x + sl[i][q].y * w.y, cur.tg, j * FB, q * NSL * FB);
-                        if constexpr (SIDE == SIDE_OUT) {
-                            zero_tap |= cur.valid && (tl[i][q] == 0.0f);
-                            w = scale(w, filter_factor(tl[i][q], a.div, Nf));
-                        }
+                        if constexpr (SIDE == SIDE_OUT) w = scale(w, tl[i][q]);
                         st_c(w, cur.out, j * CB, q * NSL * CB);
                     });
                 }

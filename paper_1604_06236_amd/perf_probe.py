@@ -24,6 +24,8 @@ def main():
                              "split_fp16", "differentiation", "decimated", "all"])
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--copy-mib", type=int, default=256)
+    ap.add_argument("--config", default=None,
+                    help="workload for forward/adjoint/forward_adjoint (default: plain_gpu)")
     args = ap.parse_args()
 
     import numpy as np
@@ -44,10 +46,10 @@ def main():
         for w in ("forward_adjoint", "ragged", "split_bf16", "split_fp16", "differentiation", "decimated"):
             run(w, args.reps, T, W, np, torch)
         return
-    run(args.what, args.reps, T, W, np, torch)
+    run(args.what, args.reps, T, W, np, torch, args.config)
 
 
-def run(what, reps, T, W, np, torch):
+def run(what, reps, T, W, np, torch, config=None):
     dev = "cuda"
     if what == "decimated":
         c = W.CONFIGS["plain_gpu"]
@@ -79,7 +81,7 @@ def run(what, reps, T, W, np, torch):
               flush=True)
         return
     cfg = {"split_bf16": "precision", "split_fp16": "precision",
-           "differentiation": "differentiation"}.get(what, "plain_gpu")
+           "differentiation": "differentiation"}.get(what, config or "plain_gpu")
     c = W.CONFIGS[cfg]
     S_h, taps_h = W.make_uniform(c)
     S = torch.from_numpy(S_h).to(dev)
