@@ -25,35 +25,52 @@ if ROOT not in sys.path:
 STANDARD = [(16, 5, 65536), (128, 15, 4096), (256, 9, 8192), (1024, 15, 2048)]
 
 
-def tune_shape(T, K, M, B, caps=(0, 1024, 2048), reps=20, nbuf=4, verbose=True):
+def _time_pairs(torch, calls, reps, rounds=3):
+    """Seconds per forward + adjoint pair: HIP events around `reps` back-to-back
+    pairs rotating over the buffer sets; the minimum over `rounds` runs."""
+    best = float("inf")
+    for _ in range(rounds):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for i in range(reps):
+            fwd, adj = calls[i % len(calls)]
+            fwd()
+            adj()
+        ev1.record()
+        torch.cuda.synchronize()
+        best = min(best, ev0.elapsed_time(ev1) * 1e-3 / reps)
+    return best
+
+
+def tune_shape(T, K, M, B, caps=(0, 1024, 2048), reps=50, nbuf=4, verbose=True):
+    """Time every compiled schedule of (K, M) at several grid caps on a batch of B
+    blocks: forward S -> y and adjoint yb -> sb over `nbuf` rotating buffer sets
+    (separate buffers, so neither direction reads what the other just touched)."""
     import torch
     N = K * M
     dev = "cuda"
     taps = torch.rand(N, device=dev) + 0.5
-    sets = [(torch.randn(B, N, dtype=torch.complex64, device=dev),
-             torch.empty(B, N, dtype=torch.complex64, device=dev)) for _ in range(nbuf)]
+    sets = [tuple(torch.randn(B, N, dtype=torch.complex64, device=dev) for _ in range(4))
+            for _ in range(nbuf)]
     results = []
     for idx, desc in enumerate(T.schedules(K, M)):
         for cap in caps:
             T.select_schedule(K, M, idx, cap)
-            calls = [(T.bind_forward(x, taps, K, M, y), T.bind_adjoint(x, taps, K, M, y))
-                     for (x, y) in sets]
-            for i in range(3):
+            calls = [(T.bind_forward(S, taps, K, M, y), T.bind_adjoint(yb, taps, K, M, sb))
+                     for (S, y, yb, sb) in sets]
+            for i in range(2 * nbuf):
                 calls[i % nbuf][0]()
                 calls[i % nbuf][1]()
             torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for i in range(reps):
-                calls[i % nbuf][0]()
-                calls[i % nbuf][1]()
-            torch.cuda.synchronize()
-            t = (time.perf_counter() - t0) / reps
+            t = _time_pairs(torch, calls, reps)
             results.append({"schedule": idx, "grid_cap": cap, "us_fwd_adj": round(t * 1e6, 2),
                             "GBps": round(2 * 16.0 * N * B / t / 1e9, 1), **desc})
             if verbose:
                 print(f"K={K} M={M} sched={idx} cap={cap} {desc['radices']} TB={desc['threads_per_block']} "
                       f"BPW={desc['blocks_per_workgroup']} pf={desc['prefetch']} "
-                      f"seq={desc['sequential_twiddles']}: {t * 1e6:.1f} us", flush=True)
+                      f"seq={desc['sequential_twiddles']} paired={desc['paired_io']} nt={desc['nontemporal']}: "
+                      f"{t * 1e6:.1f} us", flush=True)
     best = min(results, key=lambda r: r["us_fwd_adj"])
     T.select_schedule(K, M, best["schedule"], best["grid_cap"])
     return best, results
@@ -96,7 +113,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=None, help="write the selections here (JSON)")
     ap.add_argument("--report", default=None, help="write every timing here (JSON)")
-    ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--reps", type=int, default=50)
     args = ap.parse_args()
     from paper_1604_06236_amd import transform as T
     from paper_1604_06236_amd import _native as nat

@@ -230,9 +230,10 @@ __device__ __forceinline__ c32x2 ld_c2(rsrc_t r, uint32_t voff, uint32_t soff)
     return __builtin_bit_cast(c32x2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, AUX));
 }
 
+template <int AUX = 0>
 __device__ __forceinline__ float ld_f(rsrc_t r, uint32_t voff, uint32_t soff)
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, AUX));
 }
 
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
@@ -258,9 +259,10 @@ __device__ __forceinline__ f32x2 ld_f2(rsrc_t r, uint32_t voff, uint32_t soff)
     return __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
 }
 
+template <int AUX = 0>
 __device__ __forceinline__ void st_f(float v, rsrc_t r, uint32_t voff, uint32_t soff)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, soff, AUX);
 }
 
 // ------------------------------------------------------------------ element ops

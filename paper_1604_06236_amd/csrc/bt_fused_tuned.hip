@@ -30,6 +30,8 @@ void register_fused_tuned(std::vector<FusedEntry> &v)
         make_entry<Radices<15, 8, 8, 16>, 1024, 1, OPT_NO_PREFETCH | OPT_SEQ_TWIDDLE>(1024, 15),
         make_entry<Radices<15, 16, 16, 4>, 1024, 1, OPT_SEQ_TWIDDLE>(1024, 15),
         make_entry<Radices<15, 32, 32>, 512, 1, OPT_NO_PREFETCH | OPT_SEQ_TWIDDLE>(1024, 15),
+        make_entry<Radices<15, 8, 8, 16>, 1024, 1, OPT_SEQ_TWIDDLE>(1024, 15),
+        make_entry<Radices<15, 8, 8, 16>, 1024, 1, OPT_SEQ_TWIDDLE | OPT_NT>(1024, 15),
         // K = 128, M = 15 and K = 256, M = 9 with sequential twiddles
         make_entry<Radices<15, 16, 8>, 128, 1, OPT_SEQ_TWIDDLE>(128, 15),
         make_entry<Radices<9, 16, 16>, 256, 1, OPT_SEQ_TWIDDLE>(256, 9),

@@ -75,6 +75,7 @@ __device__ __forceinline__ void ragged_chunk(const RaggedArgs &a, const RaggedIt
     constexpr uint32_t CB = 8, FB = 4;
     constexpr bool CONJ = SIDE == SIDE_OUT;
     constexpr int OPT = OPT_SEQ_TWIDDLE;
+    constexpr int NT = 2;      // non-temporal policy for the streamed operands
     const float Nf = float(N);
 
     // the thread index goes through an opaque move so that the per-class
@@ -138,8 +139,8 @@ __device__ __forceinline__ void ragged_chunk(const RaggedArgs &a, const RaggedIt
             if (FULL0 || j < NB0) {
                 static_for<0, R0>([&](auto rI) {
                     constexpr int q = decltype(rI)::value;
-                    x0[i][q] = ld_c(r.in, j * CB, q * NB0 * CB);
-                    if constexpr (SIDE == SIDE_IN) t0[i][q] = ld_f(r.taps, j * FB, q * NB0 * FB);
+                    x0[i][q] = ld_c<NT>(r.in, j * CB, q * NB0 * CB);
+                    if constexpr (SIDE == SIDE_IN) t0[i][q] = ld_f<NT>(r.taps, j * FB, q * NB0 * FB);
                 });
             }
         }
@@ -182,15 +183,15 @@ __device__ __forceinline__ void ragged_chunk(const RaggedArgs &a, const RaggedIt
                         constexpr int q = decltype(rI)::value;
                         c32 w = CONJ ? conj(v0[i][q]) : v0[i][q];
                         if constexpr (TGR) {
-                            const c32 sv = ld_c(cur.aux, j * CB, q * NB0 * CB);
-                            st_f(sv.x * w.x + sv.y * w.y, cur.tg, j * FB, q * NB0 * FB);
+                            const c32 sv = ld_c<NT>(cur.aux, j * CB, q * NB0 * CB);
+                            st_f<NT>(sv.x * w.x + sv.y * w.y, cur.tg, j * FB, q * NB0 * FB);
                         }
                         if constexpr (SIDE == SIDE_OUT) {
-                            const float tv = ld_f(cur.taps, j * FB, q * NB0 * FB);
+                            const float tv = ld_f<NT>(cur.taps, j * FB, q * NB0 * FB);
                             zero_tap |= cur.valid && (tv == 0.0f);
                             w = scale(w, filter_factor(tv, a.div, Nf));
                         }
-                        st_c(w, cur.out, j * CB, q * NB0 * CB);
+                        st_c<NT>(w, cur.out, j * CB, q * NB0 * CB);
                     });
                 }
             }
@@ -217,8 +218,8 @@ __device__ __forceinline__ void ragged_chunk(const RaggedArgs &a, const RaggedIt
                 if (FULLL || j < NBL) {
                     static_for<0, RL>([&](auto rI) {
                         constexpr int q = decltype(rI)::value;
-                        if constexpr (SIDE == SIDE_OUT) tl[i][q] = ld_f(cur.taps, j * FB, q * NSL * FB);
-                        if constexpr (TGR) sl[i][q] = ld_c(cur.aux, j * CB, q * NSL * CB);
+                        if constexpr (SIDE == SIDE_OUT) tl[i][q] = ld_f<NT>(cur.taps, j * FB, q * NSL * FB);
+                        if constexpr (TGR) sl[i][q] = ld_c<NT>(cur.aux, j * CB, q * NSL * CB);
                     });
                 }
             }
@@ -242,9 +243,9 @@ __device__ __forceinline__ void ragged_chunk(const RaggedArgs &a, const RaggedIt
                     static_for<0, RL>([&](auto rI) {
                         constexpr int q = decltype(rI)::value;
                         c32 w = CONJ ? conj(v[q]) : v[q];
-                        if constexpr (TGR) st_f(sl[i][q].x * w.x + sl[i][q].y * w.y, cur.tg, j * FB, q * NSL * FB);
+                        if constexpr (TGR) st_f<NT>(sl[i][q].x * w.x + sl[i][q].y * w.y, cur.tg, j * FB, q * NSL * FB);
                         if constexpr (SIDE == SIDE_OUT) w = scale(w, tl[i][q]);
-                        st_c(w, cur.out, j * CB, q * NSL * CB);
+                        st_c<NT>(w, cur.out, j * CB, q * NSL * CB);
                     });
                 }
             }
@@ -279,19 +280,20 @@ template <int K, int M> struct RTune {
         static constexpr bool PF_FWD = FWD_, PF_TG = TG_, PF_ADJ = ADJ_;  \
     };
 BT_RTUNE(64, 9, true, true, true, true)
-BT_RTUNE(64, 15, true, true, false, true)
+BT_RTUNE(64, 15, false, true, false, true)
 BT_RTUNE(128, 9, false, true, false, true)
-BT_RTUNE(128, 15, false, false, false, true)
+BT_RTUNE(128, 15, false, true, false, true)
 BT_RTUNE(256, 3, false, true, false, true)
 BT_RTUNE(256, 5, false, true, false, true)
 BT_RTUNE(256, 7, false, true, false, true)
 BT_RTUNE(256, 9, false, true, false, true)
-BT_RTUNE(256, 15, false, false, false, true)
+BT_RTUNE(256, 15, false, true, false, true)
 BT_RTUNE(512, 9, true, true, true, true)
 BT_RTUNE(512, 15, true, true, false, true)
+BT_RTUNE(1024, 5, false, true, false, true)
 BT_RTUNE(1024, 7, false, true, false, true)
 BT_RTUNE(1024, 9, false, true, false, true)
-BT_RTUNE(1024, 15, false, false, false, false)
+BT_RTUNE(1024, 15, false, true, false, false)
 #undef BT_RTUNE
 
 template <int K, int M>
