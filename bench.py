@@ -39,18 +39,18 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(name: str, launch_bytes: float):
+def measured_traffic(name: str, schedule):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources (null otherwise)."""
+    was taken on the current kernel sources and the same schedule (null otherwise)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
             d = json.load(f)
         e = d[name]
-        if e.get("kernel_hash") != kernel_hash():
+        if e.get("kernel_hash") != kernel_hash() or e.get("schedule") != list(schedule):
             return None
         return float(e["hbm_bytes_per_launch"])
-    except (OSError, KeyError, ValueError):
+    except (OSError, KeyError, ValueError, TypeError):
         return None
 
 
@@ -138,7 +138,7 @@ def main():
     achieved = fwd_bytes / (fwd_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic("fused_forward_128x15", fwd_bytes),
+                "traffic": measured_traffic("fused_forward_128x15", T.selected_schedule(K, M)[:2]),
                 "kernel": "fused_kernel (forward), schedule %s" % json.dumps(T.selected_schedule(K, M)[2]),
                 "kernel_ms": round(fwd_ms, 5), "adjoint_kernel_ms": round(adj_ms, 5),
                 "algorithmic_bytes_per_launch": fwd_bytes,
