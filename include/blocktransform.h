@@ -225,6 +225,53 @@ int transform_ragged_execute(tf_ragged_plan plan, int32_t direction, const void 
                              const float *taps, void *out, const void *aux, float *taps_bar,
                              int32_t *status_dev, int32_t use_graph, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Non-iterative type-5 and type-4 NFFT methods (Secs. "Computation of the
+ * type-5 NFFT" / "Computation of the type-4 NFFT"), batched over independent
+ * problems of P instants each.  The non-uniform steps are exact type-1/type-2
+ * sums; the regular-grid steps are the block transforms above (the decimated
+ * eq. (7) operator with the taps of eq. (41) for eq. (28); the inverse with the
+ * damping filter of eq. (8) for eq. (43) and eq. (31); the forward with it for
+ * eq. (37)).  Shared arguments:
+ *   t        in : instants, float64 [nblocks][P], read modulo 1 (the sums are
+ *                 1-periodic in t); converted to 64-bit fixed point on the device
+ *   nblocks     : problems in the batch, 1..65535
+ *   P           : instants per problem, a power of two in [16, 1024]
+ *   eta         : oversampling of eq. (28), R = eta P, 1..16
+ *   a           : damping of the shifted grid q/P + ja, > 0; eq. (49) ties it
+ *                 to the truncation ratio mu = e^{-2 pi (eta P - 1) a}/(eta P - 1)
+ *   workspace   : device scratch of nufft_workspace_size(nblocks, P, eta)
+ *                 bytes, 256-byte aligned, owned by the caller
+ * Arithmetic: exact fixed-point phases, FP32 terms, FP64 accumulation of the
+ * non-uniform sums, FP32 everywhere else.  All work is asynchronous on
+ * `stream`; errors are reported before any launch (TF_EINVAL for bad pointers,
+ * overlaps or a, TF_EUNSUPPORTED for P/eta outside the ranges, TF_EWORKSPACE).
+ * --------------------------------------------------------------------------- */
+size_t nufft_workspace_size(int64_t nblocks, int32_t P, int32_t eta);
+
+/* type 5 (inverse of eq. (34), the system eq. (48)): coefficients S_p, p < P,
+   from samples s(t_q).  samples in: complex64 [nblocks][P]; coeffs out: same. */
+int nufft_type5(const double *t, const void *samples, void *coeffs, int64_t nblocks, int32_t P,
+                int32_t eta, double a, void *workspace, size_t workspace_bytes, void *stream);
+
+/* type 4 (inverse of eq. (32), the system eq. (47) with p = 0..P-1): amplitudes
+   a_q from the spectrum A(r), r < P.  spectrum in / amplitudes out: complex64
+   [nblocks][P]. */
+int nufft_type4(const double *t, const void *spectrum, void *amplitudes, int64_t nblocks, int32_t P,
+                int32_t eta, double a, void *workspace, size_t workspace_bytes, void *stream);
+
+/* exact type-1 sum, eq. (32): out[b][r] = sum_{q<Q} amp[b][q] e^{-j 2 pi r t[b][q]}, r < R.
+   t: float64 [nblocks][Q]; amp: complex64 [nblocks][Q], NULL for unit amplitudes;
+   out: complex64 [nblocks][R].  Q in [1, 1024], R in [1, 65536]. */
+int nudft_type1(const double *t, const void *amp, void *out, int64_t nblocks, int32_t Q, int32_t R,
+                void *stream);
+
+/* exact type-2 sum, eq. (34): out[b][q] = sum_{p<P} coeffs[b][p] e^{+j 2 pi p t[b][q]}, q < Q.
+   t: float64 [nblocks][Q]; coeffs: complex64 [nblocks][P]; out: complex64 [nblocks][Q].
+   P in [1, 1024], Q in [1, 65536]. */
+int nudft_type2(const double *t, const void *coeffs, void *out, int64_t nblocks, int32_t P, int32_t Q,
+                void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -35,6 +35,7 @@ EXPORTED = (
     "transform_load_schedule", "transform_save_schedule",
     "transform_ragged_plan_create", "transform_ragged_plan_create_ex", "transform_ragged_plan_destroy",
     "transform_ragged_execute", "transform_decimated", "transform_decimated_adjoint",
+    "nufft_workspace_size", "nufft_type5", "nufft_type4", "nudft_type1", "nudft_type2",
 )
 
 _lib = None
@@ -82,6 +83,12 @@ def load() -> ctypes.CDLL:
     lib.transform_ragged_plan_create_ex.argtypes = [vp, vp, vp, vp, i64, i64, i32, ctypes.POINTER(vp)]
     lib.transform_ragged_plan_destroy.argtypes = [vp]
     lib.transform_ragged_execute.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, i32, vp]
+    lib.nufft_workspace_size.argtypes = [i64, i32, i32]
+    lib.nufft_workspace_size.restype = sz
+    lib.nufft_type5.argtypes = [vp, vp, vp, i64, i32, i32, ctypes.c_double, vp, sz, vp]
+    lib.nufft_type4.argtypes = [vp, vp, vp, i64, i32, i32, ctypes.c_double, vp, sz, vp]
+    lib.nudft_type1.argtypes = [vp, vp, vp, i64, i32, i32, vp]
+    lib.nudft_type2.argtypes = [vp, vp, vp, i64, i32, i32, vp]
     for name in EXPORTED:
         f = getattr(lib, name)
         if f.restype is ctypes.c_int:   # default

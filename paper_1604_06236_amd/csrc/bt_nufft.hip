@@ -1,0 +1,386 @@
+// Non-iterative type-5 and type-4 NFFT methods (Secs. "Computation of the
+// type-5 NFFT" and "Computation of the type-4 NFFT", the type-5 and type-4 flow
+// figures) on the GPU, batched over independent problems of P instants each.
+//
+// The non-uniform steps are exact type-1 / type-2 sums (eq. (32), eq. (34)),
+// O(P R) per problem; the regular-grid steps are the block transforms of this
+// library: eq. (28) is the decimated eq. (7) operator with the log-series taps
+// of eq. (41), eq. (43) and eq. (31) are the inverse with the damping taps of
+// eq. (8), eq. (37) is the forward with the same taps (M = 1).
+//
+// Numerics.  Instants are turned into 64-bit fixed-point fractions of a cycle,
+// so every phase k t_q mod 1 is formed exactly in integer arithmetic (a 32 x 32
+// high product plus a wrapping multiply-add) before one FP32 sincospi of a
+// remainder of at most 1/8 cycle; the sums of such terms accumulate in FP64
+// (MI355X runs FP64 vector FMA at the FP32 rate).  The constant phase
+// P pi + 2 pi sum t of eq. (29) is likewise summed exactly as a fixed-point
+// fraction.  Everything else is FP32.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "../../include/blocktransform.h"
+#include "bt_api_internal.hpp"
+#include "bt_fused.hpp"
+
+namespace bt {
+
+constexpr int NU_MAXP = 1024;     // instants / coefficients staged per problem
+
+// frac(t) as a fixed-point fraction of a cycle: T = frac(t) 2^64
+__device__ __forceinline__ uint64_t fixed_instant(double t)
+{
+    double f = t - floor(t);
+    if (!(f < 1.0)) f = 0.0;          // t just below an integer rounds up to 1.0; NaN -> 0
+    return (uint64_t)(f * 18446744073709551616.0);
+}
+
+// top 32 bits of frac(k t) for an integer k >= 0: (k T mod 2^64) >> 32
+__device__ __forceinline__ uint32_t phase32(uint32_t k, uint32_t tlo, uint32_t thi)
+{
+    return __umulhi(k, tlo) + k * thi;
+}
+
+// exp(+j 2 pi ph / 2^32).  The quadrant is split off exactly in integer
+// arithmetic (nearest multiple of 2^30), so the FP32 argument of sincospi is a
+// remainder of at most 1/8 cycle and keeps 24 significant bits of it.
+__device__ __forceinline__ c32 cis_rev(uint32_t ph)
+{
+    const uint32_t quad = (ph + 0x20000000u) >> 30;              // nearest quarter cycle
+    const int32_t rem = int32_t(ph - (quad << 30));               // |rem| <= 2^29
+    float s, c;
+    sincospif(float(rem) * 0x1p-31f, &s, &c);                     // rem / 2^32 cycles, times 2
+    switch (quad & 3u) {
+    case 0: return c32{c, s};
+    case 1: return c32{-s, c};
+    case 2: return c32{-c, -s};
+    default: return c32{s, -c};
+    }
+}
+
+// ------------------------------------------------------------------ type-1 sums
+// out[b][r] = sum_{q<Q} amp[b][q] exp(-j 2 pi r t[b][q]),  r < R  (eq. (32));
+// amp == nullptr means unit amplitudes (the delta train z(t) of eq. (14)).
+// Grid: (ceil(R / (TPB RPT)), nblocks); each thread owns RPT outputs.
+template <int TPB, int RPT>
+__global__ void __launch_bounds__(TPB) nudft1_kernel(const double *t, const c32 *amp, c32 *out, int Q, int R)
+{
+    __shared__ uint32_t s_lo[NU_MAXP], s_hi[NU_MAXP];
+    __shared__ c32 s_a[NU_MAXP];
+    const int64_t b = blockIdx.y;
+    for (int q = threadIdx.x; q < Q; q += TPB) {
+        const uint64_t T = fixed_instant(t[b * Q + q]);
+        s_lo[q] = uint32_t(T);
+        s_hi[q] = uint32_t(T >> 32);
+        s_a[q] = amp ? amp[b * Q + q] : c32{1.f, 0.f};
+    }
+    __syncthreads();
+    const int r0 = blockIdx.x * (TPB * RPT) + threadIdx.x;
+    double ax[RPT], ay[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) ax[i] = ay[i] = 0.0;
+    for (int q = 0; q < Q; ++q) {
+        const uint32_t lo = s_lo[q], hi = s_hi[q];
+        const c32 A = s_a[q];
+        const double Ax = A.x, Ay = A.y;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            const uint32_t r = uint32_t(r0 + i * TPB);
+            const c32 e = cis_rev(0u - phase32(r, lo, hi));         // exp(-j 2 pi r t_q)
+            const double ex = e.x, ey = e.y;
+            ax[i] = fma(Ax, ex, fma(-Ay, ey, ax[i]));
+            ay[i] = fma(Ax, ey, fma(Ay, ex, ay[i]));
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        const int r = r0 + i * TPB;
+        if (r < R) out[b * R + r] = c32{float(ax[i]), float(ay[i])};
+    }
+}
+
+// ------------------------------------------------------------------ type-2 sums
+// out[b][q] = sum_{p<P} c_p exp(+j 2 pi p t[b][q]),  q < Q  (eq. (34)).
+// deriv == 0: c_p = coef[b][p].  deriv == 1: the coefficients of L'(z) from the
+// P lower coefficients of the monic L (eq. (16)): c_p = (p+1) coef[b][p+1] for
+// p < P-1, c_{P-1} = P (L_P = 1).  Grid: (ceil(Q / TPB), nblocks).
+template <int TPB>
+__global__ void __launch_bounds__(TPB) nudft2_kernel(const double *t, const c32 *coef, c32 *out, int P, int Q,
+                                                     int deriv)
+{
+    __shared__ c32 s_c[NU_MAXP];
+    const int64_t b = blockIdx.y;
+    for (int p = threadIdx.x; p < P; p += TPB) {
+        c32 c;
+        if (!deriv) {
+            c = coef[b * P + p];
+        } else if (p + 1 < P) {
+            const c32 l = coef[b * P + p + 1];
+            c = c32{float(p + 1) * l.x, float(p + 1) * l.y};
+        } else {
+            c = c32{float(P), 0.f};
+        }
+        s_c[p] = c;
+    }
+    __syncthreads();
+    const int q = blockIdx.x * TPB + threadIdx.x;
+    if (q >= Q) return;
+    const uint64_t T = fixed_instant(t[b * Q + q]);
+    const uint32_t lo = uint32_t(T), hi = uint32_t(T >> 32);
+    double ax = 0.0, ay = 0.0;
+    for (int p = 0; p < P; ++p) {
+        const c32 e = cis_rev(phase32(uint32_t(p), lo, hi));
+        const c32 c = s_c[p];
+        const double ex = e.x, ey = e.y, cx = c.x, cy = c.y;
+        ax = fma(cx, ex, fma(-cy, ey, ax));
+        ay = fma(cx, ey, fma(cy, ex, ay));
+    }
+    out[b * Q + q] = c32{float(ax), float(ay)};
+}
+
+// ------------------------------------------------------------------ pointwise steps
+// g of eq. (41) (R taps) and the damping filter exp(-2 pi p a) of eq. (8) (P taps)
+__global__ void nufft_taps_kernel(float *g, int R, float *damp, int P, double a)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const double two_pi = 6.283185307179586476925286766559;
+    if (i < R) g[i] = (i == 0) ? 0.f : float(-exp(-two_pi * a * double(i)) / double(i));
+    if (i < P) damp[i] = float(exp(-two_pi * a * double(i)));
+}
+
+// kernel samples eq. (29): Lk_q = exp(j P pi + j 2 pi sum_p t_p + v_q); one
+// workgroup per problem, the constant phase summed exactly in fixed point
+template <int TPB>
+__global__ void __launch_bounds__(TPB) nufft_kernel_samples(const double *t, const c32 *v, c32 *Lk, int P)
+{
+    __shared__ uint64_t s_sum[TPB];
+    const int64_t b = blockIdx.x;
+    uint64_t acc = 0;
+    for (int q = threadIdx.x; q < P; q += TPB) acc += fixed_instant(t[b * P + q]);
+    s_sum[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = TPB / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s_sum[threadIdx.x] += s_sum[threadIdx.x + w];
+        __syncthreads();
+    }
+    // P pi = 2 pi (P / 2): half a cycle when P is odd
+    const uint64_t c0 = s_sum[0] + ((P & 1) ? (uint64_t(1) << 63) : 0);
+    const double rev0 = double(c0 >> 11) * 0x1p-53;                 // in [0, 1)
+    const double inv_two_pi = 0.15915494309189533576888376337251;
+    for (int q = threadIdx.x; q < P; q += TPB) {
+        const c32 vq = v[b * P + q];
+        double rev = rev0 + double(vq.y) * inv_two_pi;
+        rev -= rint(rev);                                            // [-1/2, 1/2]
+        float s, c;
+        sincospif(float(2.0 * rev), &s, &c);
+        const float m = expf(vq.x);
+        Lk[b * P + q] = c32{m * c, m * s};
+    }
+}
+
+// delta-train weights, eq. (27) / eq. (40):
+//   out_q = x_q h(-P t_q + j P a) / (L'(e^{j 2 pi t_q}) e^{j 2 pi t_q}),
+//   h(-P t + j P a) = 1 / (rho e^{-j 2 pi P t} - 1),  rho = e^{-2 pi P a}
+__global__ void nufft_weights_kernel(const double *t, const c32 *Ld, const c32 *x, c32 *out, int P,
+                                     int64_t total, float rho)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const uint64_t T = fixed_instant(t[i]);
+    const uint32_t lo = uint32_t(T), hi = uint32_t(T >> 32);
+    const c32 eP = cis_rev(0u - phase32(uint32_t(P), lo, hi));     // e^{-j 2 pi P t}
+    const c32 e1 = cis_rev(hi);                                      // e^{+j 2 pi t}
+    const c32 hd = c32{rho * eP.x - 1.f, rho * eP.y};               // 1 / h
+    const c32 d = Ld[i];
+    const c32 de = c32{d.x * e1.x - d.y * e1.y, d.x * e1.y + d.y * e1.x};
+    const c32 den = c32{hd.x * de.x - hd.y * de.y, hd.x * de.y + hd.y * de.x};
+    const float inv = 1.f / (den.x * den.x + den.y * den.y);
+    const c32 xv = x[i];
+    out[i] = c32{(xv.x * den.x + xv.y * den.y) * inv, (xv.y * den.x - xv.x * den.y) * inv};
+}
+
+// element-wise product, eq. (30)
+__global__ void nufft_cmul_kernel(const c32 *a, const c32 *b, c32 *out, int64_t total)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const c32 x = a[i], y = b[i];
+    out[i] = c32{x.x * y.x - x.y * y.y, x.x * y.y + x.y * y.x};
+}
+
+// ------------------------------------------------------------------ host side
+constexpr int NU1_TPB = 256, NU1_RPT = 4, NU2_TPB = 256, NU_PW_TPB = 256;
+
+static bool nu_aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+static int nu_check_launch(const char *what)
+{
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error(what, e);
+        return TF_EHIP;
+    }
+    return TF_OK;
+}
+
+static int nudft1_launch(const double *t, const c32 *amp, c32 *out, int64_t nblocks, int Q, int R, hipStream_t s)
+{
+    const unsigned gx = unsigned((R + NU1_TPB * NU1_RPT - 1) / (NU1_TPB * NU1_RPT));
+    hipLaunchKernelGGL((nudft1_kernel<NU1_TPB, NU1_RPT>), dim3(gx, unsigned(nblocks)), dim3(NU1_TPB), 0, s, t, amp,
+                       out, Q, R);
+    return nu_check_launch("nudft_type1 launch");
+}
+
+static int nudft2_launch(const double *t, const c32 *coef, c32 *out, int64_t nblocks, int P, int Q, int deriv,
+                         hipStream_t s)
+{
+    const unsigned gx = unsigned((Q + NU2_TPB - 1) / NU2_TPB);
+    hipLaunchKernelGGL((nudft2_kernel<NU2_TPB>), dim3(gx, unsigned(nblocks)), dim3(NU2_TPB), 0, s, t, coef, out, P,
+                       Q, deriv);
+    return nu_check_launch("nudft_type2 launch");
+}
+
+static bool nu_blocks_ok(int64_t nblocks) { return nblocks >= 1 && nblocks <= 65535; }
+
+// workspace layout, each segment 256-byte aligned
+struct NuLayout {
+    size_t g, damp, Z, v, Lk, Lc, Ld, t1, t2, total;
+};
+
+static size_t nu_round(size_t x) { return (x + 255) & ~size_t(255); }
+
+static NuLayout nu_layout(int64_t nblocks, int P, int eta)
+{
+    NuLayout l{};
+    const size_t R = size_t(P) * eta, BP = size_t(nblocks) * P * sizeof(c32);
+    size_t o = 0;
+    l.g = o;    o += nu_round(R * sizeof(float));
+    l.damp = o; o += nu_round(size_t(P) * sizeof(float));
+    l.Z = o;    o += nu_round(size_t(nblocks) * R * sizeof(c32));
+    l.v = o;    o += nu_round(BP);
+    l.Lk = o;   o += nu_round(BP);
+    l.Lc = o;   o += nu_round(BP);
+    l.Ld = o;   o += nu_round(BP);
+    l.t1 = o;   o += nu_round(BP);
+    l.t2 = o;   o += nu_round(BP);
+    l.total = o;
+    return l;
+}
+
+static bool nu_shape_ok(int P, int eta)
+{
+    return P >= 16 && P <= 1024 && (P & (P - 1)) == 0 && eta >= 1 && eta <= 16;
+}
+
+// kind 5: in = samples s(t_q), out = coefficients S_p (type-5 flow)
+// kind 4: in = spectral samples A(r), out = amplitudes a_q (type-4 flow)
+static int nufft_run(int kind, const double *t, const void *in, void *out, int64_t nblocks, int P, int eta,
+                     double a, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!nu_shape_ok(P, eta)) return TF_EUNSUPPORTED;
+    if (!nu_blocks_ok(nblocks) || !(a > 0.0) || !std::isfinite(a)) return TF_EINVAL;
+    if (!t || !in || !out || !nu_aligned(t, 8) || !nu_aligned(in, 8) || !nu_aligned(out, 8)) return TF_EINVAL;
+    const NuLayout l = nu_layout(nblocks, P, eta);
+    if (!ws || ws_bytes < l.total || !nu_aligned(ws, 256)) return TF_EWORKSPACE;
+    const size_t io_bytes = size_t(nblocks) * P * sizeof(c32);
+    const uintptr_t pw = reinterpret_cast<uintptr_t>(ws), po = reinterpret_cast<uintptr_t>(out),
+                    pi = reinterpret_cast<uintptr_t>(in), pt = reinterpret_cast<uintptr_t>(t);
+    const size_t t_bytes = size_t(nblocks) * P * sizeof(double);
+    auto ov = [](uintptr_t x, size_t xb, uintptr_t y, size_t yb) { return x < y + yb && y < x + xb; };
+    if (ov(po, io_bytes, pw, l.total) || ov(pi, io_bytes, pw, l.total) || ov(pt, t_bytes, pw, l.total) ||
+        ov(po, io_bytes, pt, t_bytes))
+        return TF_EINVAL;
+
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(ws);
+    float *g = reinterpret_cast<float *>(w + l.g);
+    float *damp = reinterpret_cast<float *>(w + l.damp);
+    c32 *Z = reinterpret_cast<c32 *>(w + l.Z), *v = reinterpret_cast<c32 *>(w + l.v);
+    c32 *Lk = reinterpret_cast<c32 *>(w + l.Lk), *Lc = reinterpret_cast<c32 *>(w + l.Lc);
+    c32 *Ld = reinterpret_cast<c32 *>(w + l.Ld), *t1 = reinterpret_cast<c32 *>(w + l.t1);
+    c32 *t2 = reinterpret_cast<c32 *>(w + l.t2);
+    const int R = P * eta;
+    const int64_t BP = nblocks * P;
+    const unsigned pw_grid = unsigned((BP + NU_PW_TPB - 1) / NU_PW_TPB);
+    const float rho = float(std::exp(-2.0 * M_PI * double(P) * a));
+    int rc;
+
+    // filters of eq. (41) and eq. (8)
+    hipLaunchKernelGGL(nufft_taps_kernel, dim3(unsigned((R + 255) / 256)), dim3(256), 0, s, g, R, damp, P, a);
+    if ((rc = nu_check_launch("nufft taps launch"))) return rc;
+    // eq. (28): unit delta train -> spectrum at 0..R-1 -> decimated eq. (7) with g
+    if ((rc = nudft1_launch(t, nullptr, Z, nblocks, P, R, s))) return rc;
+    if ((rc = transform_decimated(Z, g, v, nblocks, P, eta, 0, stream))) return rc;
+    // eq. (29): kernel samples on the shifted grid
+    hipLaunchKernelGGL((nufft_kernel_samples<256>), dim3(unsigned(nblocks)), dim3(256), 0, s, t, v, Lk, P);
+    if ((rc = nu_check_launch("nufft kernel samples launch"))) return rc;
+    // eq. (43): L_p = e^{2 pi p a} DFT(Lk)_p / P for p >= 1 (the alias fix touches L_0 only,
+    // which the derivative of eq. (16) never reads)
+    if ((rc = transform_inverse(Lk, damp, Lc, nblocks, P, 1, 0, TF_FP32, nullptr, nullptr, 0, stream))) return rc;
+    // eq. (16): L'(e^{j 2 pi t_q}) by a type-2 sum
+    if ((rc = nudft2_launch(t, Lc, Ld, nblocks, P, P, 1, s))) return rc;
+
+    const c32 *x = reinterpret_cast<const c32 *>(in);
+    c32 *y = reinterpret_cast<c32 *>(out);
+    if (kind == 5) {
+        // eq. (27) weights -> type-1 sum -> eq. (37): the summation eq. (25)
+        hipLaunchKernelGGL(nufft_weights_kernel, dim3(pw_grid), dim3(NU_PW_TPB), 0, s, t, Ld, x, t1, P, BP, rho);
+        if ((rc = nu_check_launch("nufft weights launch"))) return rc;
+        if ((rc = nudft1_launch(t, t1, t2, nblocks, P, P, s))) return rc;
+        if ((rc = transform_forward(t2, damp, t1, nblocks, P, 1, 0, TF_FP32, nullptr, 0, stream))) return rc;
+        // eq. (30), then eq. (31)
+        hipLaunchKernelGGL(nufft_cmul_kernel, dim3(pw_grid), dim3(NU_PW_TPB), 0, s, Lk, t1, t2, BP);
+        if ((rc = nu_check_launch("nufft product launch"))) return rc;
+        return transform_inverse(t2, damp, y, nblocks, P, 1, 0, TF_FP32, nullptr, nullptr, 0, stream);
+    }
+    // type 4: eq. (37) -> eq. (30) -> eq. (31) -> type-2 sum -> eq. (40)
+    if ((rc = transform_forward(x, damp, t1, nblocks, P, 1, 0, TF_FP32, nullptr, 0, stream))) return rc;
+    hipLaunchKernelGGL(nufft_cmul_kernel, dim3(pw_grid), dim3(NU_PW_TPB), 0, s, Lk, t1, t2, BP);
+    if ((rc = nu_check_launch("nufft product launch"))) return rc;
+    if ((rc = transform_inverse(t2, damp, t1, nblocks, P, 1, 0, TF_FP32, nullptr, nullptr, 0, stream))) return rc;
+    if ((rc = nudft2_launch(t, t1, t2, nblocks, P, P, 0, s))) return rc;
+    hipLaunchKernelGGL(nufft_weights_kernel, dim3(pw_grid), dim3(NU_PW_TPB), 0, s, t, Ld, t2, y, P, BP, rho);
+    return nu_check_launch("nufft weights launch");
+}
+
+} // namespace bt
+
+using namespace bt;
+
+extern "C" size_t nufft_workspace_size(int64_t nblocks, int32_t P, int32_t eta)
+{
+    if (!nu_shape_ok(P, eta) || !nu_blocks_ok(nblocks)) return 0;
+    return nu_layout(nblocks, P, eta).total;
+}
+
+extern "C" int nufft_type5(const double *t, const void *samples, void *coeffs, int64_t nblocks, int32_t P,
+                           int32_t eta, double a, void *workspace, size_t workspace_bytes, void *stream)
+{
+    return nufft_run(5, t, samples, coeffs, nblocks, P, eta, a, workspace, workspace_bytes, stream);
+}
+
+extern "C" int nufft_type4(const double *t, const void *spectrum, void *amplitudes, int64_t nblocks, int32_t P,
+                           int32_t eta, double a, void *workspace, size_t workspace_bytes, void *stream)
+{
+    return nufft_run(4, t, spectrum, amplitudes, nblocks, P, eta, a, workspace, workspace_bytes, stream);
+}
+
+extern "C" int nudft_type1(const double *t, const void *amp, void *out, int64_t nblocks, int32_t Q, int32_t R,
+                           void *stream)
+{
+    if (Q < 1 || Q > NU_MAXP || R < 1 || R > 65536 || !nu_blocks_ok(nblocks)) return TF_EUNSUPPORTED;
+    if (!t || !out || !nu_aligned(t, 8) || !nu_aligned(out, 8) || (amp && !nu_aligned(amp, 8))) return TF_EINVAL;
+    return nudft1_launch(t, reinterpret_cast<const c32 *>(amp), reinterpret_cast<c32 *>(out), nblocks, Q, R,
+                         reinterpret_cast<hipStream_t>(stream));
+}
+
+extern "C" int nudft_type2(const double *t, const void *coeffs, void *out, int64_t nblocks, int32_t P, int32_t Q,
+                           void *stream)
+{
+    if (P < 1 || P > NU_MAXP || Q < 1 || Q > 65536 || !nu_blocks_ok(nblocks)) return TF_EUNSUPPORTED;
+    if (!t || !coeffs || !out || !nu_aligned(t, 8) || !nu_aligned(coeffs, 8) || !nu_aligned(out, 8))
+        return TF_EINVAL;
+    return nudft2_launch(t, reinterpret_cast<const c32 *>(coeffs), reinterpret_cast<c32 *>(out), nblocks, P, Q, 0,
+                         reinterpret_cast<hipStream_t>(stream));
+}

@@ -1,0 +1,150 @@
+"""GPU type-1 / type-2 sums and the type-5 / type-4 methods against the FP64
+oracle (oracle/lagrange.py) and Gaussian elimination.
+
+Tolerances.  The sums use exact fixed-point phases, FP32 terms and FP64
+accumulation: relative error a few FP32 ulps (bound 2e-6 here).  The methods run
+every regular-grid step in FP32; eq. (43) multiplies the FP32 rounding of the
+kernel samples by up to amp = exp(2 pi a (P - 1)) (the damping compensation),
+so the GPU-vs-oracle tolerance is 4e-6 * amp (a few FP32 ulps times the
+log2 P depth of the transforms, times amp).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import lagrange as L
+from paper_1604_06236_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1604_06236_amd import nufft as NU
+    from paper_1604_06236_amd import _native as nat
+    return torch, NU, nat
+
+
+def cn(rng, shape):
+    return ((rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / np.sqrt(2)).astype(np.complex64)
+
+
+def inst(B, P, seed):
+    rng = np.random.default_rng(seed)
+    return np.stack([W.jittered_instants(rng, P) for _ in range(B)])
+
+
+def dev(torch, x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+@pytest.mark.parametrize("Q,R,unit", [(64, 384, False), (100, 1000, False), (1, 7, False), (256, 4096, True),
+                                      (1024, 1024, False)])
+def test_type1_sum_matches_oracle(env, Q, R, unit):
+    torch, NU, _ = env
+    B = 3
+    t = inst(B, Q, Q + R)
+    rng = np.random.default_rng(R)
+    amp = None if unit else cn(rng, (B, Q))
+    out = NU.nudft_type1(dev(torch, t), None if unit else dev(torch, amp), R).cpu().numpy()
+    for b in range(B):
+        ref = L.type1(t[b], np.ones(Q) if unit else amp[b], R)
+        assert L.rel_err(out[b], ref) < 2e-6
+
+
+@pytest.mark.parametrize("P,Q", [(64, 64), (64, 77), (1024, 300), (5, 1)])
+def test_type2_sum_matches_oracle(env, P, Q):
+    torch, NU, _ = env
+    B = 2
+    t = inst(B, Q, 7 * P + Q)
+    c = cn(np.random.default_rng(P), (B, P))
+    out = NU.nudft_type2(dev(torch, t), dev(torch, c)).cpu().numpy()
+    for b in range(B):
+        assert L.rel_err(out[b], L.type2(c[b], t[b])) < 2e-6
+
+
+def test_sums_read_instants_modulo_one(env):
+    torch, NU, _ = env
+    t = inst(2, 64, 3)
+    shifted = t + np.array([[3.0], [-2.0]])
+    amp = cn(np.random.default_rng(4), (2, 64))
+    a1 = NU.nudft_type1(dev(torch, t), dev(torch, amp), 256).cpu().numpy()
+    a2 = NU.nudft_type1(dev(torch, shifted), dev(torch, amp), 256).cpu().numpy()
+    assert L.rel_err(a2, a1) < 1e-6
+
+
+def amp_of(a, P):
+    return math.exp(2 * math.pi * a * (P - 1))
+
+
+@pytest.mark.parametrize("P,eta,mu", [(16, 6, 1e-7), (64, 1, 1e-7), (64, 6, 1e-7), (256, 15, 1e-7),
+                                      (1024, 6, 1e-7), (1024, 15, 1e-6)])
+def test_methods_match_oracle(env, P, eta, mu):
+    torch, NU, _ = env
+    B = 3 if P < 1024 else 2
+    a = NU.damping_for(mu, eta, P)
+    t = inst(B, P, 11 * P + eta)
+    rng = np.random.default_rng(P + eta)
+    s = cn(rng, (B, P))
+    A = cn(rng, (B, P))
+    S_gpu = NU.nufft_type5(dev(torch, t), dev(torch, s), eta, a).cpu().numpy()
+    a_gpu = NU.nufft_type4(dev(torch, t), dev(torch, A), eta, a).cpu().numpy()
+    tol = 4e-6 * amp_of(a, P)
+    for b in range(B):
+        st = L.Setup(t[b], eta, a)
+        assert L.rel_err(S_gpu[b], L.type5_method(t[b], s[b], eta, a, st)) < tol
+        assert L.rel_err(a_gpu[b], L.type4_method(t[b], A[b], eta, a, st)) < tol
+
+
+def test_methods_solve_the_systems(env):
+    """At P = 64, eta = 6 the GPU solutions agree with Gaussian elimination on
+    eq. (48) / eq. (47) to the method's truncation error plus the FP32 bound."""
+    torch, NU, _ = env
+    P, eta, mu, B = 64, 6, 1e-7, 4
+    a = NU.damping_for(mu, eta, P)
+    t = inst(B, P, 99)
+    rng = np.random.default_rng(5)
+    s = cn(rng, (B, P))
+    A = cn(rng, (B, P))
+    S_gpu = NU.nufft_type5(dev(torch, t), dev(torch, s), eta, a).cpu().numpy()
+    a_gpu = NU.nufft_type4(dev(torch, t), dev(torch, A), eta, a).cpu().numpy()
+    for b in range(B):
+        e5 = L.rel_err(L.type5_method(t[b], s[b], eta, a), L.ge_type5(t[b], s[b]))
+        e4 = L.rel_err(L.type4_method(t[b], A[b], eta, a), L.ge_type4(t[b], A[b]))
+        tol = 4e-6 * amp_of(a, P)
+        assert L.rel_err(S_gpu[b], L.ge_type5(t[b], s[b])) < e5 + tol
+        assert L.rel_err(a_gpu[b], L.ge_type4(t[b], A[b])) < e4 + tol
+
+
+def test_full_size_batch_sampled(env):
+    """64 problems of P = 1024 at eta = 6 (the benchmarked shape), two checked
+    against the oracle."""
+    torch, NU, _ = env
+    B, P, eta, mu = 64, 1024, 6, 1e-7
+    a = NU.damping_for(mu, eta, P)
+    t = inst(B, P, 2024)
+    s = cn(np.random.default_rng(6), (B, P))
+    S_gpu = NU.nufft_type5(dev(torch, t), dev(torch, s), eta, a).cpu().numpy()
+    assert np.all(np.isfinite(S_gpu))
+    for b in (0, B - 1):
+        assert L.rel_err(S_gpu[b], L.type5_method(t[b], s[b], eta, a)) < 4e-6 * amp_of(a, P)
+
+
+def test_errors_are_reported_before_launch(env):
+    torch, NU, nat = env
+    lib = nat.load()
+    t = dev(torch, inst(1, 64, 1))
+    x = dev(torch, cn(np.random.default_rng(1), (1, 64)))
+    y = torch.empty_like(x)
+    ws = torch.empty(NU.nufft_workspace_size(1, 64, 6), dtype=torch.uint8, device="cuda")
+    P = NU._ptr
+    assert lib.nufft_type5(P(t), P(x), P(y), 1, 48, 6, 0.01, P(ws), ws.numel(), None) == nat.TF_EUNSUPPORTED
+    assert lib.nufft_type5(P(t), P(x), P(y), 1, 64, 17, 0.01, P(ws), ws.numel(), None) == nat.TF_EUNSUPPORTED
+    assert lib.nufft_type5(P(t), P(x), P(y), 1, 64, 6, 0.0, P(ws), ws.numel(), None) == nat.TF_EINVAL
+    assert lib.nufft_type5(P(t), P(x), P(y), 1, 64, 6, 0.01, P(ws), 16, None) == nat.TF_EWORKSPACE
+    assert lib.nudft_type1(P(t), P(x), P(y), 1, 0, 64, None) == nat.TF_EUNSUPPORTED
+    assert lib.nudft_type2(P(t), P(x), P(y), 1, 2048, 64, None) == nat.TF_EUNSUPPORTED
+    torch.cuda.synchronize()
