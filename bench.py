@@ -372,6 +372,43 @@ def extras(T, W, args):
                               "frac_hbm_peak": round(byts / t / 1e9 / HBM_PEAK_GBS, 4),
                               "workload": "8192 blocks K=256 M=9, forward + adjoint with the "
                                           "deterministic shared tap-gradient reduction"}
+
+    # ---- non-iterative type-5 / type-4 methods: 256 problems of P = 1024 jittered
+    #      instants, eta = 6, truncation ratio mu = 1e-7 (eq. (49))
+    from oracle import lagrange as LG
+    from paper_1604_06236_amd import nufft as NU
+    B, P, eta, mu = 256, 1024, 6, 1e-7
+    a = NU.damping_for(mu, eta, P)
+    rng = np.random.default_rng(11)
+    t_h = np.stack([W.jittered_instants(rng, P) for _ in range(B)])
+    s_h = W.cn01(rng, (B, P)).astype(np.complex64)
+    A_h = W.cn01(rng, (B, P)).astype(np.complex64)
+    tt = torch.from_numpy(t_h).to(dev)
+    s = torch.from_numpy(s_h).to(dev)
+    A = torch.from_numpy(A_h).to(dev)
+    S5 = torch.empty_like(s)
+    a4 = torch.empty_like(A)
+    ws = torch.empty(NU.nufft_workspace_size(B, P, eta), dtype=torch.uint8, device=dev)
+
+    def nstep(i):
+        NU.nufft_type5(tt, s, eta, a, out=S5, workspace=ws)
+        NU.nufft_type4(tt, A, eta, a, out=a4, workspace=ws)
+
+    t = _timeit(nstep, max(3, steps // 10))
+    # exact non-uniform sum terms per step: each method does eta P^2 (eq. (28)) + P^2 (eq. (16))
+    # + P^2 (the weights' type-1 sum, or the type-2 evaluation of s(t_q))
+    terms = 2 * B * (eta + 2) * P * P
+    st = LG.Setup(t_h[0], eta, a)
+    S_ref = LG.type5_method(t_h[0], s_h[0], eta, a, st)
+    a_ref = LG.type4_method(t_h[0], A_h[0], eta, a, st)
+    res["nufft"] = {"solves_per_s": round(2 * B / t, 1), "ms_per_step": round(t * 1e3, 4),
+                    "nudft_terms_per_s": float(f"{terms / t:.4g}"),
+                    "rel_l2_type5_vs_oracle": _rel(S5.cpu().numpy()[0], S_ref),
+                    "rel_l2_type4_vs_oracle": _rel(a4.cpu().numpy()[0], a_ref),
+                    "rel_l2_type5_vs_gaussian_elimination": _rel(S5.cpu().numpy()[0], LG.ge_type5(t_h[0], s_h[0])),
+                    "oracle_method_vs_gaussian_elimination": _rel(S_ref, LG.ge_type5(t_h[0], s_h[0])),
+                    "workload": f"{B} problems of P={P} jittered instants (p/P + U[0, 0.6/P]), eta={eta}, "
+                                f"mu={mu:g} (a={a:.4g}); one type-5 and one type-4 solve each per step"}
     return res
 
 
