@@ -186,6 +186,27 @@ def type4_method(t, A, eta, a, setup: Setup | None = None):
     return type2(S, st.t) * st.wf                                           # eq. (40)
 
 
+def type4_refined(t, A, eta, a, setup: Setup | None = None):
+    """Refined type-4 method (Sec. 5, eq. (44)-(46)): a first pass a0, the type-1
+    sum of a0 minus the data (the error the method left in the spectrum, step 1-2),
+    the method applied to that residual (step 3), subtracted from a0 (step 4)."""
+    st = setup or Setup(t, eta, a)
+    A = np.asarray(A, np.complex128)
+    a0 = type4_method(t, A, eta, a, st)
+    resid = type1(st.t, a0, st.P) - A
+    return a0 - type4_method(t, resid, eta, a, st)
+
+
+def type5_refined(t, s, eta, a, setup: Setup | None = None):
+    """Refined type-5 method (the same residual correction, with the type-2
+    evaluation of eq. (34) as the forward map)."""
+    st = setup or Setup(t, eta, a)
+    s = np.asarray(s, np.complex128)
+    S0 = type5_method(t, s, eta, a, st)
+    resid = type2(S0, st.t) - s
+    return S0 - type5_method(t, resid, eta, a, st)
+
+
 def rel_err(x, ref):
     """Relative quadratic-norm error of the numerical section."""
     x = np.asarray(x)

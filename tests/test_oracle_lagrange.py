@@ -197,3 +197,39 @@ def test_pins_catch_planted_mistakes(monkeypatch):
         m.setattr(L, "derivative_samples", deriv_no_factor)
         st = L.Setup(t, eta, a)
         assert L.rel_err(st.Ld, exact_derivative(t)) > 0.1
+
+
+# ------------------------------------------------------------ refined methods (Sec. 5)
+@pytest.mark.parametrize("eta,mu", [(1, 1e-4), (2, 1e-4), (1, 1e-6), (2, 1e-6)])
+def test_refinement_squares_the_error(eta, mu):
+    """eq. (45)-(46): if one pass has relative error eps, the refined method has
+    about eps^2 (measured against Gaussian elimination)."""
+    P = 64
+    rng = np.random.default_rng(eta * 7 + int(-np.log10(mu)))
+    t = instants(P, seed=eta + 100)
+    A = cn(rng, P)
+    s = cn(rng, P)
+    a = L.damping_for(mu, eta, P)
+    st = L.Setup(t, eta, a)
+    for method, refined, ge, x in ((L.type4_method, L.type4_refined, L.ge_type4, A),
+                                   (L.type5_method, L.type5_refined, L.ge_type5, s)):
+        ref = ge(t, x)
+        e1 = L.rel_err(method(t, x, eta, a, st), ref)
+        e2 = L.rel_err(refined(t, x, eta, a, st), ref)
+        assert e2 < 10 * e1 * e1 + 1e-12
+        assert e2 < e1 / 20
+
+
+def test_refinement_residual_is_the_system_residual(monkeypatch):
+    """A refinement that forgets to subtract the data (step 2) is caught."""
+    P, eta, mu = 64, 2, 1e-4
+    t = instants(P, seed=77)
+    A = cn(np.random.default_rng(77), P)
+    a = L.damping_for(mu, eta, P)
+    good = L.rel_err(L.type4_refined(t, A, eta, a), L.ge_type4(t, A))
+    real_type1 = L.type1
+    with monkeypatch.context() as m:
+        m.setattr(L, "type1", lambda tt, amp, R: real_type1(tt, amp, R) + A if R == P and amp is not None
+                  and np.asarray(amp).dtype == np.complex128 and len(amp) == P else real_type1(tt, amp, R))
+        bad = L.rel_err(L.type4_refined(t, A, eta, a), L.ge_type4(t, A))
+    assert good < 1e-4 and bad > 0.5
