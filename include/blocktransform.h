@@ -260,6 +260,17 @@ int nufft_type5(const double *t, const void *samples, void *coeffs, int64_t nblo
 int nufft_type4(const double *t, const void *spectrum, void *amplitudes, int64_t nblocks, int32_t P,
                 int32_t eta, double a, void *workspace, size_t workspace_bytes, void *stream);
 
+/* the refined methods of Sec. 5 (eq. (44)-(46)): one pass of the method, the
+   residual of the system computed with the exact type-2 (type 5) or type-1
+   (type 4) sum, a second pass on the residual, subtracted.  The relative error
+   of one pass, eps, becomes about eps^2 (down to the FP32 floor).  Same
+   arguments as above; the input and output must not overlap. */
+int nufft_type5_refined(const double *t, const void *samples, void *coeffs, int64_t nblocks, int32_t P,
+                        int32_t eta, double a, void *workspace, size_t workspace_bytes, void *stream);
+int nufft_type4_refined(const double *t, const void *spectrum, void *amplitudes, int64_t nblocks,
+                        int32_t P, int32_t eta, double a, void *workspace, size_t workspace_bytes,
+                        void *stream);
+
 /* exact type-1 sum, eq. (32): out[b][r] = sum_{q<Q} amp[b][q] e^{-j 2 pi r t[b][q]}, r < R.
    t: float64 [nblocks][Q]; amp: complex64 [nblocks][Q], NULL for unit amplitudes;
    out: complex64 [nblocks][R].  Q in [1, 1024], R in [1, 65536]. */

@@ -35,7 +35,8 @@ EXPORTED = (
     "transform_load_schedule", "transform_save_schedule",
     "transform_ragged_plan_create", "transform_ragged_plan_create_ex", "transform_ragged_plan_destroy",
     "transform_ragged_execute", "transform_decimated", "transform_decimated_adjoint",
-    "nufft_workspace_size", "nufft_type5", "nufft_type4", "nudft_type1", "nudft_type2",
+    "nufft_workspace_size", "nufft_type5", "nufft_type4", "nufft_type5_refined", "nufft_type4_refined",
+    "nudft_type1", "nudft_type2",
 )
 
 _lib = None
@@ -87,6 +88,8 @@ def load() -> ctypes.CDLL:
     lib.nufft_workspace_size.restype = sz
     lib.nufft_type5.argtypes = [vp, vp, vp, i64, i32, i32, ctypes.c_double, vp, sz, vp]
     lib.nufft_type4.argtypes = [vp, vp, vp, i64, i32, i32, ctypes.c_double, vp, sz, vp]
+    lib.nufft_type5_refined.argtypes = [vp, vp, vp, i64, i32, i32, ctypes.c_double, vp, sz, vp]
+    lib.nufft_type4_refined.argtypes = [vp, vp, vp, i64, i32, i32, ctypes.c_double, vp, sz, vp]
     lib.nudft_type1.argtypes = [vp, vp, vp, i64, i32, i32, vp]
     lib.nudft_type2.argtypes = [vp, vp, vp, i64, i32, i32, vp]
     for name in EXPORTED:

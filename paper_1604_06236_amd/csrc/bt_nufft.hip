@@ -209,6 +209,15 @@ __global__ void nufft_cmul_kernel(const c32 *a, const c32 *b, c32 *out, int64_t 
     out[i] = c32{x.x * y.x - x.y * y.y, x.x * y.y + x.y * y.x};
 }
 
+// y += alpha x (residual and correction of the refinement, eq. (44)-(46))
+__global__ void nufft_axpy_kernel(c32 *y, const c32 *x, float alpha, int64_t total)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const c32 a = y[i], b = x[i];
+    y[i] = c32{a.x + alpha * b.x, a.y + alpha * b.y};
+}
+
 // ------------------------------------------------------------------ host side
 constexpr int NU1_TPB = 256, NU1_RPT = 4, NU2_TPB = 256, NU_PW_TPB = 256;
 
@@ -245,7 +254,7 @@ static bool nu_blocks_ok(int64_t nblocks) { return nblocks >= 1 && nblocks <= 65
 
 // workspace layout, each segment 256-byte aligned
 struct NuLayout {
-    size_t g, damp, Z, v, Lk, Lc, Ld, t1, t2, total;
+    size_t g, damp, Z, v, Lk, Lc, Ld, t1, t2, t3, t4, total;
 };
 
 static size_t nu_round(size_t x) { return (x + 255) & ~size_t(255); }
@@ -264,6 +273,8 @@ static NuLayout nu_layout(int64_t nblocks, int P, int eta)
     l.Ld = o;   o += nu_round(BP);
     l.t1 = o;   o += nu_round(BP);
     l.t2 = o;   o += nu_round(BP);
+    l.t3 = o;   o += nu_round(BP);
+    l.t4 = o;   o += nu_round(BP);
     l.total = o;
     return l;
 }
@@ -273,10 +284,74 @@ static bool nu_shape_ok(int P, int eta)
     return P >= 16 && P <= 1024 && (P & (P - 1)) == 0 && eta >= 1 && eta <= 16;
 }
 
-// kind 5: in = samples s(t_q), out = coefficients S_p (type-5 flow)
-// kind 4: in = spectral samples A(r), out = amplitudes a_q (type-4 flow)
-static int nufft_run(int kind, const double *t, const void *in, void *out, int64_t nblocks, int P, int eta,
-                     double a, void *ws, size_t ws_bytes, void *stream)
+struct NuBufs {
+    float *g, *damp;
+    c32 *Z, *v, *Lk, *Lc, *Ld, *t1, *t2, *t3, *t4;
+};
+
+// the part of both methods that depends on the instants only: filters, kernel
+// samples (eq. (28), eq. (29)), Lagrange coefficients (eq. (43)) and derivative
+// samples (eq. (16))
+static int nu_setup(const double *t, int64_t nblocks, int P, int eta, double a, const NuBufs &b, void *stream)
+{
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int R = P * eta;
+    int rc;
+    // filters of eq. (41) and eq. (8)
+    hipLaunchKernelGGL(nufft_taps_kernel, dim3(unsigned((R + 255) / 256)), dim3(256), 0, s, b.g, R, b.damp, P, a);
+    if ((rc = nu_check_launch("nufft taps launch"))) return rc;
+    // eq. (28): unit delta train -> spectrum at 0..R-1 -> decimated eq. (7) with g
+    if ((rc = nudft1_launch(t, nullptr, b.Z, nblocks, P, R, s))) return rc;
+    if ((rc = transform_decimated(b.Z, b.g, b.v, nblocks, P, eta, 0, stream))) return rc;
+    // eq. (29): kernel samples on the shifted grid
+    hipLaunchKernelGGL((nufft_kernel_samples<256>), dim3(unsigned(nblocks)), dim3(256), 0, s, t, b.v, b.Lk, P);
+    if ((rc = nu_check_launch("nufft kernel samples launch"))) return rc;
+    // eq. (43): L_p = e^{2 pi p a} DFT(Lk)_p / P for p >= 1 (the alias fix touches L_0 only,
+    // which the derivative of eq. (16) never reads)
+    if ((rc = transform_inverse(b.Lk, b.damp, b.Lc, nblocks, P, 1, 0, TF_FP32, nullptr, nullptr, 0, stream)))
+        return rc;
+    // eq. (16): L'(e^{j 2 pi t_q}) by a type-2 sum
+    return nudft2_launch(t, b.Lc, b.Ld, nblocks, P, P, 1, s);
+}
+
+// kind 5: x = samples s(t_q) -> y = coefficients S_p (type-5 flow)
+// kind 4: x = spectral samples A(r) -> y = amplitudes a_q (type-4 flow)
+static int nu_apply(int kind, const double *t, const c32 *x, c32 *y, int64_t nblocks, int P, double a,
+                    const NuBufs &b, void *stream)
+{
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int64_t BP = nblocks * P;
+    const unsigned pw_grid = unsigned((BP + NU_PW_TPB - 1) / NU_PW_TPB);
+    const float rho = float(std::exp(-2.0 * M_PI * double(P) * a));
+    int rc;
+    if (kind == 5) {
+        // eq. (27) weights -> type-1 sum -> eq. (37): the summation eq. (25)
+        hipLaunchKernelGGL(nufft_weights_kernel, dim3(pw_grid), dim3(NU_PW_TPB), 0, s, t, b.Ld, x, b.t1, P, BP, rho);
+        if ((rc = nu_check_launch("nufft weights launch"))) return rc;
+        if ((rc = nudft1_launch(t, b.t1, b.t2, nblocks, P, P, s))) return rc;
+        if ((rc = transform_forward(b.t2, b.damp, b.t1, nblocks, P, 1, 0, TF_FP32, nullptr, 0, stream))) return rc;
+        // eq. (30), then eq. (31)
+        hipLaunchKernelGGL(nufft_cmul_kernel, dim3(pw_grid), dim3(NU_PW_TPB), 0, s, b.Lk, b.t1, b.t2, BP);
+        if ((rc = nu_check_launch("nufft product launch"))) return rc;
+        return transform_inverse(b.t2, b.damp, y, nblocks, P, 1, 0, TF_FP32, nullptr, nullptr, 0, stream);
+    }
+    // type 4: eq. (37) -> eq. (30) -> eq. (31) -> type-2 sum -> eq. (40)
+    if ((rc = transform_forward(x, b.damp, b.t1, nblocks, P, 1, 0, TF_FP32, nullptr, 0, stream))) return rc;
+    hipLaunchKernelGGL(nufft_cmul_kernel, dim3(pw_grid), dim3(NU_PW_TPB), 0, s, b.Lk, b.t1, b.t2, BP);
+    if ((rc = nu_check_launch("nufft product launch"))) return rc;
+    if ((rc = transform_inverse(b.t2, b.damp, b.t1, nblocks, P, 1, 0, TF_FP32, nullptr, nullptr, 0, stream)))
+        return rc;
+    if ((rc = nudft2_launch(t, b.t1, b.t2, nblocks, P, P, 0, s))) return rc;
+    hipLaunchKernelGGL(nufft_weights_kernel, dim3(pw_grid), dim3(NU_PW_TPB), 0, s, t, b.Ld, b.t2, y, P, BP, rho);
+    return nu_check_launch("nufft weights launch");
+}
+
+// refine == 0: one pass of the method.  refine == 1: the refined method of
+// Sec. 5 (eq. (44)-(46)): y0 = method(x); residual r = F y0 - x with F the
+// forward map of the system (the type-1 sum for type 4, the type-2 evaluation
+// for type 5); y = y0 - method(r).  The setup is shared by both passes.
+static int nufft_run(int kind, int refine, const double *t, const void *in, void *out, int64_t nblocks, int P,
+                     int eta, double a, void *ws, size_t ws_bytes, void *stream)
 {
     if (!nu_shape_ok(P, eta)) return TF_EUNSUPPORTED;
     if (!nu_blocks_ok(nblocks) || !(a > 0.0) || !std::isfinite(a)) return TF_EINVAL;
@@ -291,57 +366,42 @@ static int nufft_run(int kind, const double *t, const void *in, void *out, int64
     if (ov(po, io_bytes, pw, l.total) || ov(pi, io_bytes, pw, l.total) || ov(pt, t_bytes, pw, l.total) ||
         ov(po, io_bytes, pt, t_bytes))
         return TF_EINVAL;
+    // the refinement reads the input again after the first pass has written the output
+    if (refine && ov(po, io_bytes, pi, io_bytes)) return TF_EINVAL;
 
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     char *w = static_cast<char *>(ws);
-    float *g = reinterpret_cast<float *>(w + l.g);
-    float *damp = reinterpret_cast<float *>(w + l.damp);
-    c32 *Z = reinterpret_cast<c32 *>(w + l.Z), *v = reinterpret_cast<c32 *>(w + l.v);
-    c32 *Lk = reinterpret_cast<c32 *>(w + l.Lk), *Lc = reinterpret_cast<c32 *>(w + l.Lc);
-    c32 *Ld = reinterpret_cast<c32 *>(w + l.Ld), *t1 = reinterpret_cast<c32 *>(w + l.t1);
-    c32 *t2 = reinterpret_cast<c32 *>(w + l.t2);
-    const int R = P * eta;
-    const int64_t BP = nblocks * P;
-    const unsigned pw_grid = unsigned((BP + NU_PW_TPB - 1) / NU_PW_TPB);
-    const float rho = float(std::exp(-2.0 * M_PI * double(P) * a));
-    int rc;
-
-    // filters of eq. (41) and eq. (8)
-    hipLaunchKernelGGL(nufft_taps_kernel, dim3(unsigned((R + 255) / 256)), dim3(256), 0, s, g, R, damp, P, a);
-    if ((rc = nu_check_launch("nufft taps launch"))) return rc;
-    // eq. (28): unit delta train -> spectrum at 0..R-1 -> decimated eq. (7) with g
-    if ((rc = nudft1_launch(t, nullptr, Z, nblocks, P, R, s))) return rc;
-    if ((rc = transform_decimated(Z, g, v, nblocks, P, eta, 0, stream))) return rc;
-    // eq. (29): kernel samples on the shifted grid
-    hipLaunchKernelGGL((nufft_kernel_samples<256>), dim3(unsigned(nblocks)), dim3(256), 0, s, t, v, Lk, P);
-    if ((rc = nu_check_launch("nufft kernel samples launch"))) return rc;
-    // eq. (43): L_p = e^{2 pi p a} DFT(Lk)_p / P for p >= 1 (the alias fix touches L_0 only,
-    // which the derivative of eq. (16) never reads)
-    if ((rc = transform_inverse(Lk, damp, Lc, nblocks, P, 1, 0, TF_FP32, nullptr, nullptr, 0, stream))) return rc;
-    // eq. (16): L'(e^{j 2 pi t_q}) by a type-2 sum
-    if ((rc = nudft2_launch(t, Lc, Ld, nblocks, P, P, 1, s))) return rc;
-
+    NuBufs b;
+    b.g = reinterpret_cast<float *>(w + l.g);
+    b.damp = reinterpret_cast<float *>(w + l.damp);
+    b.Z = reinterpret_cast<c32 *>(w + l.Z);
+    b.v = reinterpret_cast<c32 *>(w + l.v);
+    b.Lk = reinterpret_cast<c32 *>(w + l.Lk);
+    b.Lc = reinterpret_cast<c32 *>(w + l.Lc);
+    b.Ld = reinterpret_cast<c32 *>(w + l.Ld);
+    b.t1 = reinterpret_cast<c32 *>(w + l.t1);
+    b.t2 = reinterpret_cast<c32 *>(w + l.t2);
+    b.t3 = reinterpret_cast<c32 *>(w + l.t3);
+    b.t4 = reinterpret_cast<c32 *>(w + l.t4);
     const c32 *x = reinterpret_cast<const c32 *>(in);
     c32 *y = reinterpret_cast<c32 *>(out);
-    if (kind == 5) {
-        // eq. (27) weights -> type-1 sum -> eq. (37): the summation eq. (25)
-        hipLaunchKernelGGL(nufft_weights_kernel, dim3(pw_grid), dim3(NU_PW_TPB), 0, s, t, Ld, x, t1, P, BP, rho);
-        if ((rc = nu_check_launch("nufft weights launch"))) return rc;
-        if ((rc = nudft1_launch(t, t1, t2, nblocks, P, P, s))) return rc;
-        if ((rc = transform_forward(t2, damp, t1, nblocks, P, 1, 0, TF_FP32, nullptr, 0, stream))) return rc;
-        // eq. (30), then eq. (31)
-        hipLaunchKernelGGL(nufft_cmul_kernel, dim3(pw_grid), dim3(NU_PW_TPB), 0, s, Lk, t1, t2, BP);
-        if ((rc = nu_check_launch("nufft product launch"))) return rc;
-        return transform_inverse(t2, damp, y, nblocks, P, 1, 0, TF_FP32, nullptr, nullptr, 0, stream);
-    }
-    // type 4: eq. (37) -> eq. (30) -> eq. (31) -> type-2 sum -> eq. (40)
-    if ((rc = transform_forward(x, damp, t1, nblocks, P, 1, 0, TF_FP32, nullptr, 0, stream))) return rc;
-    hipLaunchKernelGGL(nufft_cmul_kernel, dim3(pw_grid), dim3(NU_PW_TPB), 0, s, Lk, t1, t2, BP);
-    if ((rc = nu_check_launch("nufft product launch"))) return rc;
-    if ((rc = transform_inverse(t2, damp, t1, nblocks, P, 1, 0, TF_FP32, nullptr, nullptr, 0, stream))) return rc;
-    if ((rc = nudft2_launch(t, t1, t2, nblocks, P, P, 0, s))) return rc;
-    hipLaunchKernelGGL(nufft_weights_kernel, dim3(pw_grid), dim3(NU_PW_TPB), 0, s, t, Ld, t2, y, P, BP, rho);
-    return nu_check_launch("nufft weights launch");
+    int rc;
+    if ((rc = nu_setup(t, nblocks, P, eta, a, b, stream))) return rc;
+    if ((rc = nu_apply(kind, t, x, y, nblocks, P, a, b, stream))) return rc;
+    if (!refine) return TF_OK;
+
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int64_t BP = nblocks * P;
+    const unsigned pw_grid = unsigned((BP + NU_PW_TPB - 1) / NU_PW_TPB);
+    // residual of the first pass: F y0 - x
+    if (kind == 4) rc = nudft1_launch(t, y, b.t3, nblocks, P, P, s);
+    else rc = nudft2_launch(t, y, b.t3, nblocks, P, P, 0, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(nufft_axpy_kernel, dim3(pw_grid), dim3(NU_PW_TPB), 0, s, b.t3, x, -1.f, BP);
+    if ((rc = nu_check_launch("nufft residual launch"))) return rc;
+    // the method on the residual, subtracted from the first pass
+    if ((rc = nu_apply(kind, t, b.t3, b.t4, nblocks, P, a, b, stream))) return rc;
+    hipLaunchKernelGGL(nufft_axpy_kernel, dim3(pw_grid), dim3(NU_PW_TPB), 0, s, y, b.t4, -1.f, BP);
+    return nu_check_launch("nufft correction launch");
 }
 
 } // namespace bt
@@ -357,13 +417,26 @@ extern "C" size_t nufft_workspace_size(int64_t nblocks, int32_t P, int32_t eta)
 extern "C" int nufft_type5(const double *t, const void *samples, void *coeffs, int64_t nblocks, int32_t P,
                            int32_t eta, double a, void *workspace, size_t workspace_bytes, void *stream)
 {
-    return nufft_run(5, t, samples, coeffs, nblocks, P, eta, a, workspace, workspace_bytes, stream);
+    return nufft_run(5, 0, t, samples, coeffs, nblocks, P, eta, a, workspace, workspace_bytes, stream);
 }
 
 extern "C" int nufft_type4(const double *t, const void *spectrum, void *amplitudes, int64_t nblocks, int32_t P,
                            int32_t eta, double a, void *workspace, size_t workspace_bytes, void *stream)
 {
-    return nufft_run(4, t, spectrum, amplitudes, nblocks, P, eta, a, workspace, workspace_bytes, stream);
+    return nufft_run(4, 0, t, spectrum, amplitudes, nblocks, P, eta, a, workspace, workspace_bytes, stream);
+}
+
+extern "C" int nufft_type5_refined(const double *t, const void *samples, void *coeffs, int64_t nblocks, int32_t P,
+                                   int32_t eta, double a, void *workspace, size_t workspace_bytes, void *stream)
+{
+    return nufft_run(5, 1, t, samples, coeffs, nblocks, P, eta, a, workspace, workspace_bytes, stream);
+}
+
+extern "C" int nufft_type4_refined(const double *t, const void *spectrum, void *amplitudes, int64_t nblocks,
+                                   int32_t P, int32_t eta, double a, void *workspace, size_t workspace_bytes,
+                                   void *stream)
+{
+    return nufft_run(4, 1, t, spectrum, amplitudes, nblocks, P, eta, a, workspace, workspace_bytes, stream);
 }
 
 extern "C" int nudft_type1(const double *t, const void *amp, void *out, int64_t nblocks, int32_t Q, int32_t R,

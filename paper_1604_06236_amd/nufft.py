@@ -62,15 +62,19 @@ def _solve(fn: str, t: torch.Tensor, x: torch.Tensor, eta: int, a: float, out, w
 
 
 def nufft_type5(t: torch.Tensor, samples: torch.Tensor, eta: int, a: float, *,
-                out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None):
-    """Coefficients S [B, P] with sum_p S_p e^{j 2 pi p t_q} = samples_q (eq. (48))."""
-    return _solve("nufft_type5", t, samples, eta, a, out, workspace)
+                out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
+                refine: bool = False):
+    """Coefficients S [B, P] with sum_p S_p e^{j 2 pi p t_q} = samples_q (eq. (48));
+    `refine` runs the refined method of Sec. 5 (eq. (44)-(46))."""
+    return _solve("nufft_type5_refined" if refine else "nufft_type5", t, samples, eta, a, out, workspace)
 
 
 def nufft_type4(t: torch.Tensor, spectrum: torch.Tensor, eta: int, a: float, *,
-                out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None):
-    """Amplitudes a [B, P] with sum_q a_q e^{-j 2 pi r t_q} = spectrum_r, r < P (eq. (47))."""
-    return _solve("nufft_type4", t, spectrum, eta, a, out, workspace)
+                out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
+                refine: bool = False):
+    """Amplitudes a [B, P] with sum_q a_q e^{-j 2 pi r t_q} = spectrum_r, r < P (eq. (47));
+    `refine` runs the refined method of Sec. 5 (eq. (44)-(46))."""
+    return _solve("nufft_type4_refined" if refine else "nufft_type4", t, spectrum, eta, a, out, workspace)
 
 
 def nudft_type1(t: torch.Tensor, amp: Optional[torch.Tensor], R: int, *,

@@ -148,3 +148,38 @@ def test_errors_are_reported_before_launch(env):
     assert lib.nudft_type1(P(t), P(x), P(y), 1, 0, 64, None) == nat.TF_EUNSUPPORTED
     assert lib.nudft_type2(P(t), P(x), P(y), 1, 2048, 64, None) == nat.TF_EUNSUPPORTED
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("P,eta,mu", [(64, 2, 1e-4), (256, 1, 1e-4), (1024, 2, 1e-5)])
+def test_refined_methods(env, P, eta, mu):
+    """The refined methods of Sec. 5 against the oracle's refined methods, and
+    their gain over one pass measured against Gaussian elimination."""
+    torch, NU, _ = env
+    B = 2
+    a = NU.damping_for(mu, eta, P)
+    t = inst(B, P, 5 * P + eta)
+    rng = np.random.default_rng(3 * P + eta)
+    s = cn(rng, (B, P))
+    A = cn(rng, (B, P))
+    S1 = NU.nufft_type5(dev(torch, t), dev(torch, s), eta, a, refine=True).cpu().numpy()
+    a1 = NU.nufft_type4(dev(torch, t), dev(torch, A), eta, a, refine=True).cpu().numpy()
+    tol = 4e-6 * amp_of(a, P)
+    for b in range(B):
+        st = L.Setup(t[b], eta, a)
+        assert L.rel_err(S1[b], L.type5_refined(t[b], s[b], eta, a, st)) < tol
+        assert L.rel_err(a1[b], L.type4_refined(t[b], A[b], eta, a, st)) < tol
+        e5 = L.rel_err(L.type5_method(t[b], s[b], eta, a, st), L.ge_type5(t[b], s[b]))
+        e4 = L.rel_err(L.type4_method(t[b], A[b], eta, a, st), L.ge_type4(t[b], A[b]))
+        assert L.rel_err(S1[b], L.ge_type5(t[b], s[b])) < 0.1 * e5 + tol
+        assert L.rel_err(a1[b], L.ge_type4(t[b], A[b])) < 0.1 * e4 + tol
+
+
+def test_refined_rejects_in_place(env):
+    torch, NU, nat = env
+    lib = nat.load()
+    t = dev(torch, inst(1, 64, 1))
+    x = dev(torch, cn(np.random.default_rng(1), (1, 64)))
+    ws = torch.empty(NU.nufft_workspace_size(1, 64, 2), dtype=torch.uint8, device="cuda")
+    P = NU._ptr
+    assert lib.nufft_type4_refined(P(t), P(x), P(x), 1, 64, 2, 0.01, P(ws), ws.numel(), None) == nat.TF_EINVAL
+    torch.cuda.synchronize()
