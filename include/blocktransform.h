@@ -249,6 +249,19 @@ int transform_ragged_execute(tf_ragged_plan plan, int32_t direction, const void 
  * --------------------------------------------------------------------------- */
 size_t nufft_workspace_size(int64_t nblocks, int32_t P, int32_t eta);
 
+/* options of nufft_solve */
+enum {
+    NUFFT_REFINE = 1,    /* the refined method of Sec. 5 (eq. (44)-(46)) */
+    NUFFT_GRIDDING = 2   /* non-uniform sums by the gridding NFFTs below instead of exact
+                            sums: needs 2 eta P <= 16384 (a block-transform size) */
+};
+size_t nufft_workspace_size_ex(int64_t nblocks, int32_t P, int32_t eta, int32_t flags);
+
+/* type 4 or 5 with options; the four entry points below are its fixed-option forms */
+int nufft_solve(int32_t type, int32_t flags, const double *t, const void *in, void *out,
+                int64_t nblocks, int32_t P, int32_t eta, double a, void *workspace,
+                size_t workspace_bytes, void *stream);
+
 /* type 5 (inverse of eq. (34), the system eq. (48)): coefficients S_p, p < P,
    from samples s(t_q).  samples in: complex64 [nblocks][P]; coeffs out: same. */
 int nufft_type5(const double *t, const void *samples, void *coeffs, int64_t nblocks, int32_t P,
@@ -270,6 +283,20 @@ int nufft_type5_refined(const double *t, const void *samples, void *coeffs, int6
 int nufft_type4_refined(const double *t, const void *spectrum, void *amplitudes, int64_t nblocks,
                         int32_t P, int32_t eta, double a, void *workspace, size_t workspace_bytes,
                         void *stream);
+
+/* Gridding NFFTs (the type-1 NFFT of Sec. 2 as one gridding operation and one FFT at
+   oversampling 2; the type-2 as a weighting, an inverse FFT and a short interpolation).
+   Window: the periodised Gaussian exp(-x^2/(4 tau)) of Dutt-Rokhlin / Greengard-Lee,
+   tau = ln(1e7)/(2 pi^2 n^2), 16 grid points per instant, fine grid n = 2 band, relative
+   accuracy about 1e-7 (FP32).  The band (R for type 1, P for type 2) must be even, >= 16, with
+   2 band <= 16384 a block-transform size (K M, K a power of two <= 1024, M <= 16).
+   Same array layouts as nudft_type1 / nudft_type2; workspace of nfft_workspace_size
+   bytes, 256-byte aligned. */
+size_t nfft_workspace_size(int64_t nblocks, int32_t band);
+int nfft_type1(const double *t, const void *amp, void *out, int64_t nblocks, int32_t Q, int32_t R,
+               void *workspace, size_t workspace_bytes, void *stream);
+int nfft_type2(const double *t, const void *coeffs, void *out, int64_t nblocks, int32_t P, int32_t Q,
+               void *workspace, size_t workspace_bytes, void *stream);
 
 /* exact type-1 sum, eq. (32): out[b][r] = sum_{q<Q} amp[b][q] e^{-j 2 pi r t[b][q]}, r < R.
    t: float64 [nblocks][Q]; amp: complex64 [nblocks][Q], NULL for unit amplitudes;

@@ -218,6 +218,127 @@ __global__ void nufft_axpy_kernel(c32 *y, const c32 *x, float alpha, int64_t tot
     y[i] = c32{a.x + alpha * b.x, a.y + alpha * b.y};
 }
 
+// ------------------------------------------------------------------ gridding NFFTs
+// Type-1 / type-2 NFFTs by gridding at oversampling 2 with the Gaussian window of
+// Dutt-Rokhlin / Greengard-Lee: fine grid n = 2 (band size),
+// g(x) = exp(-x^2 / (4 tau)) periodised, tau = ln(1/eps) / (2 pi^2 n^2), kept on
+// the 2 GRID_HALF grid points around n t, g_hat(k) = sqrt(4 pi tau) exp(-4 pi^2 k^2 tau).
+// The band 0..R-1 of eq. (32) is the centred band -R/2..R/2-1 after a modulation
+// by exp(-j 2 pi (R/2) t); the FFTs are this library's transforms with the
+// deconvolution 1 / g_hat folded into their taps.  eps = 1e-7 (FP32 level).
+constexpr int GRID_HALF = 8;                         // ceil(sqrt(2) ln(1e7) / pi)
+constexpr double GRID_LOG_INV_EPS = 16.11809565095832;   // ln(1e7)
+
+// spread the (modulated) amplitudes of one problem onto its fine grid in LDS
+// (float atomics), then store the grid.  One workgroup per problem; dynamic
+// LDS of 2 n floats.
+template <int TPB>
+__global__ void __launch_bounds__(TPB) grid_spread_kernel(const double *t, const c32 *amp, c32 *grid, int Q, int n,
+                                                          int rhalf, float kappa)
+{
+    extern __shared__ float g_lds[];
+    const int64_t b = blockIdx.x;
+    for (int i = threadIdx.x; i < 2 * n; i += TPB) g_lds[i] = 0.f;
+    __syncthreads();
+    for (int q = threadIdx.x; q < Q; q += TPB) {
+        const uint64_t T = fixed_instant(t[b * Q + q]);
+        const c32 a = amp ? amp[b * Q + q] : c32{1.f, 0.f};
+        const c32 e = cis_rev(0u - phase32(uint32_t(rhalf), uint32_t(T), uint32_t(T >> 32)));
+        const c32 c = c32{a.x * e.x - a.y * e.y, a.x * e.y + a.y * e.x};
+        const double x = double(T >> 11) * 0x1p-53 * double(n);        // n t in [0, n)
+        const double fl = floor(x);
+        const int m0 = min(int(fl), n - 1);
+        const float fx = float(x - fl);
+        for (int j = -GRID_HALF + 1; j <= GRID_HALF; ++j) {
+            int m = m0 + j;
+            m = m < 0 ? m + n : (m >= n ? m - n : m);
+            const float d = fx - float(j);
+            const float w = __expf(-kappa * d * d);
+            atomicAdd(&g_lds[2 * m], c.x * w);
+            atomicAdd(&g_lds[2 * m + 1], c.y * w);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += TPB) grid[b * n + i] = c32{g_lds[2 * i], g_lds[2 * i + 1]};
+}
+
+// deconvolution taps over the n bins of the fine grid: for the bins of the
+// centred band -band/2..band/2-1, scale / g_hat(k); zero elsewhere
+__global__ void grid_taps_kernel(float *taps, int n, int band, double tau, double scale)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int k = i < n / 2 ? i : i - n;
+    const double pi = 3.14159265358979323846;
+    const bool in_band = k >= -(band / 2) && k < band - band / 2;
+    taps[i] = in_band ? float(scale * exp(4.0 * pi * pi * double(k) * double(k) * tau) / sqrt(4.0 * pi * tau))
+                      : 0.f;
+}
+
+// band 0..R-1 from the fine-grid spectrum: out[b][r] = spec[b][(r - R/2) mod n]
+__global__ void grid_pick_kernel(const c32 *spec, c32 *out, int R, int n, int64_t total)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int64_t b = i / R;
+    const int r = int(i - b * R);
+    int k = r - R / 2;
+    if (k < 0) k += n;
+    out[i] = spec[b * n + k];
+}
+
+// coefficients 0..P-1 onto the fine-grid bins of the centred band (zeros
+// elsewhere); deriv = 1 builds the coefficients of L' from L (eq. (16))
+__global__ void grid_load_kernel(const c32 *coef, c32 *H, int P, int n, int deriv, int64_t total)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int64_t b = i / n;
+    const int bin = int(i - b * n);
+    const int k = bin < n / 2 ? bin : bin - n;
+    const int p = k + P / 2;
+    c32 v = c32{0.f, 0.f};
+    if (p >= 0 && p < P) {
+        if (!deriv) {
+            v = coef[b * P + p];
+        } else if (p + 1 < P) {
+            const c32 l = coef[b * P + p + 1];
+            v = c32{float(p + 1) * l.x, float(p + 1) * l.y};
+        } else {
+            v = c32{float(P), 0.f};
+        }
+    }
+    H[i] = v;
+}
+
+// interpolation: out_q = e^{j 2 pi (P/2) t_q} (1/n) sum_j h[(m0 + j) mod n] g(t_q - (m0 + j)/n)
+__global__ void grid_interp_kernel(const double *t, const c32 *h, c32 *out, int Q, int n, int phalf, float kappa,
+                                   int64_t total)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int64_t b = i / Q;
+    const uint64_t T = fixed_instant(t[i]);
+    const double x = double(T >> 11) * 0x1p-53 * double(n);
+    const double fl = floor(x);
+    const int m0 = min(int(fl), n - 1);
+    const float fx = float(x - fl);
+    float sx = 0.f, sy = 0.f;
+    const c32 *hb = h + b * n;
+    for (int j = -GRID_HALF + 1; j <= GRID_HALF; ++j) {
+        int m = m0 + j;
+        m = m < 0 ? m + n : (m >= n ? m - n : m);
+        const float d = fx - float(j);
+        const float w = __expf(-kappa * d * d);
+        const c32 v = hb[m];
+        sx += v.x * w;
+        sy += v.y * w;
+    }
+    const c32 e = cis_rev(phase32(uint32_t(phalf), uint32_t(T), uint32_t(T >> 32)));
+    const float inv_n = 1.f / float(n);
+    out[i] = c32{(sx * e.x - sy * e.y) * inv_n, (sx * e.y + sy * e.x) * inv_n};
+}
+
 // ------------------------------------------------------------------ host side
 constexpr int NU1_TPB = 256, NU1_RPT = 4, NU2_TPB = 256, NU_PW_TPB = 256;
 
@@ -252,14 +373,92 @@ static int nudft2_launch(const double *t, const c32 *coef, c32 *out, int64_t nbl
 
 static bool nu_blocks_ok(int64_t nblocks) { return nblocks >= 1 && nblocks <= 65535; }
 
+// fine-grid size for a band of `band` frequencies and its factorisation n = K M
+// for the block transforms (K a power of two <= 1024, M <= 16)
+static bool grid_shape(int band, int *n, int *K, int *M)
+{
+    if (band < 16 || band % 2) return false;        // the window's 16 points must fit in the period
+    const int nn = 2 * band;
+    int k = 1;
+    while (k < 1024 && nn % (2 * k) == 0) k *= 2;
+    if (nn / k > 16 || !supported_km(k, nn / k)) return false;
+    *n = nn;
+    *K = k;
+    *M = nn / k;
+    return nn <= 16384;
+}
+
+static double grid_tau(int n) { return GRID_LOG_INV_EPS / (2.0 * M_PI * M_PI * double(n) * double(n)); }
+// g(d / n) = exp(-kappa d^2) for a distance of d grid cells
+static float grid_kappa() { return float(M_PI * M_PI / (2.0 * GRID_LOG_INV_EPS)); }
+
+static int grid_spread_attr()
+{
+    static int rc = [] {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&grid_spread_kernel<1024>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, 16384 * 8);
+        if (e != hipSuccess) {
+            set_error("hipFuncSetAttribute(grid spread)", e);
+            return int(TF_EHIP);
+        }
+        return int(TF_OK);
+    }();
+    return rc;
+}
+
+// gridding type-1: out[b][r], r < R, from Q instants; scratch: grid and spectrum
+// (nblocks n complex each) and n taps
+static int grid1_run(const double *t, const c32 *amp, c32 *out, int64_t nblocks, int Q, int R, c32 *grid,
+                     c32 *spec, float *taps, void *stream)
+{
+    int n, K, M, rc;
+    if (!grid_shape(R, &n, &K, &M)) return TF_EUNSUPPORTED;
+    if ((rc = grid_spread_attr())) return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const double tau = grid_tau(n);
+    hipLaunchKernelGGL(grid_taps_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, taps, n, R, tau,
+                       1.0 / double(n));
+    if ((rc = nu_check_launch("grid taps launch"))) return rc;
+    hipLaunchKernelGGL((grid_spread_kernel<1024>), dim3(unsigned(nblocks)), dim3(1024), size_t(n) * 8, s, t, amp,
+                       grid, Q, n, R / 2, grid_kappa());
+    if ((rc = nu_check_launch("grid spread launch"))) return rc;
+    if ((rc = transform_adjoint(grid, taps, nullptr, spec, nullptr, nblocks, K, M, 0, TF_FP32, nullptr, 0, stream)))
+        return rc;
+    const int64_t total = nblocks * R;
+    hipLaunchKernelGGL(grid_pick_kernel, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s, spec, out, R, n,
+                       total);
+    return nu_check_launch("grid pick launch");
+}
+
+// gridding type-2: out[b][q], q < Q, from P coefficients (deriv: those of L')
+static int grid2_run(const double *t, const c32 *coef, c32 *out, int64_t nblocks, int P, int Q, int deriv,
+                     c32 *grid, c32 *spec, float *taps, void *stream)
+{
+    int n, K, M, rc;
+    if (!grid_shape(P, &n, &K, &M)) return TF_EUNSUPPORTED;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const double tau = grid_tau(n);
+    hipLaunchKernelGGL(grid_taps_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, taps, n, P, tau, 1.0);
+    if ((rc = nu_check_launch("grid taps launch"))) return rc;
+    const int64_t tn = nblocks * n;
+    hipLaunchKernelGGL(grid_load_kernel, dim3(unsigned((tn + 255) / 256)), dim3(256), 0, s, coef, spec, P, n, deriv,
+                       tn);
+    if ((rc = nu_check_launch("grid load launch"))) return rc;
+    if ((rc = transform_forward(spec, taps, grid, nblocks, K, M, 0, TF_FP32, nullptr, 0, stream))) return rc;
+    const int64_t tq = nblocks * Q;
+    hipLaunchKernelGGL(grid_interp_kernel, dim3(unsigned((tq + 255) / 256)), dim3(256), 0, s, t, grid, out, Q, n,
+                       P / 2, grid_kappa(), tq);
+    return nu_check_launch("grid interp launch");
+}
+
 // workspace layout, each segment 256-byte aligned
 struct NuLayout {
-    size_t g, damp, Z, v, Lk, Lc, Ld, t1, t2, t3, t4, total;
+    size_t g, damp, Z, v, Lk, Lc, Ld, t1, t2, t3, t4, gg, gs, gt, total;
 };
 
 static size_t nu_round(size_t x) { return (x + 255) & ~size_t(255); }
 
-static NuLayout nu_layout(int64_t nblocks, int P, int eta)
+static NuLayout nu_layout(int64_t nblocks, int P, int eta, bool gridding = false)
 {
     NuLayout l{};
     const size_t R = size_t(P) * eta, BP = size_t(nblocks) * P * sizeof(c32);
@@ -275,6 +474,11 @@ static NuLayout nu_layout(int64_t nblocks, int P, int eta)
     l.t2 = o;   o += nu_round(BP);
     l.t3 = o;   o += nu_round(BP);
     l.t4 = o;   o += nu_round(BP);
+    // gridding scratch: fine grid and spectrum for the largest band (R), its taps
+    const size_t nmax = gridding ? 2 * R : 0;
+    l.gg = o;   o += nu_round(size_t(nblocks) * nmax * sizeof(c32));
+    l.gs = o;   o += nu_round(size_t(nblocks) * nmax * sizeof(c32));
+    l.gt = o;   o += nu_round(nmax * sizeof(float));
     l.total = o;
     return l;
 }
@@ -287,7 +491,25 @@ static bool nu_shape_ok(int P, int eta)
 struct NuBufs {
     float *g, *damp;
     c32 *Z, *v, *Lk, *Lc, *Ld, *t1, *t2, *t3, *t4;
+    c32 *gg, *gs;      // gridding scratch
+    float *gt;
+    bool grid;         // non-uniform sums by gridding instead of exact sums
 };
+
+// the non-uniform sums of the pipeline: exact, or by gridding
+static int sum1(const NuBufs &b, const double *t, const c32 *amp, c32 *out, int64_t nblocks, int Q, int R,
+                void *stream)
+{
+    if (b.grid) return grid1_run(t, amp, out, nblocks, Q, R, b.gg, b.gs, b.gt, stream);
+    return nudft1_launch(t, amp, out, nblocks, Q, R, reinterpret_cast<hipStream_t>(stream));
+}
+
+static int sum2(const NuBufs &b, const double *t, const c32 *coef, c32 *out, int64_t nblocks, int P, int Q,
+                int deriv, void *stream)
+{
+    if (b.grid) return grid2_run(t, coef, out, nblocks, P, Q, deriv, b.gg, b.gs, b.gt, stream);
+    return nudft2_launch(t, coef, out, nblocks, P, Q, deriv, reinterpret_cast<hipStream_t>(stream));
+}
 
 // the part of both methods that depends on the instants only: filters, kernel
 // samples (eq. (28), eq. (29)), Lagrange coefficients (eq. (43)) and derivative
@@ -301,7 +523,7 @@ static int nu_setup(const double *t, int64_t nblocks, int P, int eta, double a, 
     hipLaunchKernelGGL(nufft_taps_kernel, dim3(unsigned((R + 255) / 256)), dim3(256), 0, s, b.g, R, b.damp, P, a);
     if ((rc = nu_check_launch("nufft taps launch"))) return rc;
     // eq. (28): unit delta train -> spectrum at 0..R-1 -> decimated eq. (7) with g
-    if ((rc = nudft1_launch(t, nullptr, b.Z, nblocks, P, R, s))) return rc;
+    if ((rc = sum1(b, t, nullptr, b.Z, nblocks, P, R, stream))) return rc;
     if ((rc = transform_decimated(b.Z, b.g, b.v, nblocks, P, eta, 0, stream))) return rc;
     // eq. (29): kernel samples on the shifted grid
     hipLaunchKernelGGL((nufft_kernel_samples<256>), dim3(unsigned(nblocks)), dim3(256), 0, s, t, b.v, b.Lk, P);
@@ -311,7 +533,7 @@ static int nu_setup(const double *t, int64_t nblocks, int P, int eta, double a, 
     if ((rc = transform_inverse(b.Lk, b.damp, b.Lc, nblocks, P, 1, 0, TF_FP32, nullptr, nullptr, 0, stream)))
         return rc;
     // eq. (16): L'(e^{j 2 pi t_q}) by a type-2 sum
-    return nudft2_launch(t, b.Lc, b.Ld, nblocks, P, P, 1, s);
+    return sum2(b, t, b.Lc, b.Ld, nblocks, P, P, 1, stream);
 }
 
 // kind 5: x = samples s(t_q) -> y = coefficients S_p (type-5 flow)
@@ -328,7 +550,7 @@ static int nu_apply(int kind, const double *t, const c32 *x, c32 *y, int64_t nbl
         // eq. (27) weights -> type-1 sum -> eq. (37): the summation eq. (25)
         hipLaunchKernelGGL(nufft_weights_kernel, dim3(pw_grid), dim3(NU_PW_TPB), 0, s, t, b.Ld, x, b.t1, P, BP, rho);
         if ((rc = nu_check_launch("nufft weights launch"))) return rc;
-        if ((rc = nudft1_launch(t, b.t1, b.t2, nblocks, P, P, s))) return rc;
+        if ((rc = sum1(b, t, b.t1, b.t2, nblocks, P, P, stream))) return rc;
         if ((rc = transform_forward(b.t2, b.damp, b.t1, nblocks, P, 1, 0, TF_FP32, nullptr, 0, stream))) return rc;
         // eq. (30), then eq. (31)
         hipLaunchKernelGGL(nufft_cmul_kernel, dim3(pw_grid), dim3(NU_PW_TPB), 0, s, b.Lk, b.t1, b.t2, BP);
@@ -341,7 +563,7 @@ static int nu_apply(int kind, const double *t, const c32 *x, c32 *y, int64_t nbl
     if ((rc = nu_check_launch("nufft product launch"))) return rc;
     if ((rc = transform_inverse(b.t2, b.damp, b.t1, nblocks, P, 1, 0, TF_FP32, nullptr, nullptr, 0, stream)))
         return rc;
-    if ((rc = nudft2_launch(t, b.t1, b.t2, nblocks, P, P, 0, s))) return rc;
+    if ((rc = sum2(b, t, b.t1, b.t2, nblocks, P, P, 0, stream))) return rc;
     hipLaunchKernelGGL(nufft_weights_kernel, dim3(pw_grid), dim3(NU_PW_TPB), 0, s, t, b.Ld, b.t2, y, P, BP, rho);
     return nu_check_launch("nufft weights launch");
 }
@@ -350,13 +572,21 @@ static int nu_apply(int kind, const double *t, const c32 *x, c32 *y, int64_t nbl
 // Sec. 5 (eq. (44)-(46)): y0 = method(x); residual r = F y0 - x with F the
 // forward map of the system (the type-1 sum for type 4, the type-2 evaluation
 // for type 5); y = y0 - method(r).  The setup is shared by both passes.
-static int nufft_run(int kind, int refine, const double *t, const void *in, void *out, int64_t nblocks, int P,
+static bool nu_grid_ok(int P, int eta)
+{
+    int n, K, M;
+    return grid_shape(P * eta, &n, &K, &M) && grid_shape(P, &n, &K, &M);
+}
+
+static int nufft_run(int kind, int flags, const double *t, const void *in, void *out, int64_t nblocks, int P,
                      int eta, double a, void *ws, size_t ws_bytes, void *stream)
 {
-    if (!nu_shape_ok(P, eta)) return TF_EUNSUPPORTED;
+    const bool refine = flags & NUFFT_REFINE, gridding = flags & NUFFT_GRIDDING;
+    if (flags & ~(NUFFT_REFINE | NUFFT_GRIDDING)) return TF_EINVAL;
+    if (!nu_shape_ok(P, eta) || (gridding && !nu_grid_ok(P, eta))) return TF_EUNSUPPORTED;
     if (!nu_blocks_ok(nblocks) || !(a > 0.0) || !std::isfinite(a)) return TF_EINVAL;
     if (!t || !in || !out || !nu_aligned(t, 8) || !nu_aligned(in, 8) || !nu_aligned(out, 8)) return TF_EINVAL;
-    const NuLayout l = nu_layout(nblocks, P, eta);
+    const NuLayout l = nu_layout(nblocks, P, eta, gridding);
     if (!ws || ws_bytes < l.total || !nu_aligned(ws, 256)) return TF_EWORKSPACE;
     const size_t io_bytes = size_t(nblocks) * P * sizeof(c32);
     const uintptr_t pw = reinterpret_cast<uintptr_t>(ws), po = reinterpret_cast<uintptr_t>(out),
@@ -382,6 +612,10 @@ static int nufft_run(int kind, int refine, const double *t, const void *in, void
     b.t2 = reinterpret_cast<c32 *>(w + l.t2);
     b.t3 = reinterpret_cast<c32 *>(w + l.t3);
     b.t4 = reinterpret_cast<c32 *>(w + l.t4);
+    b.gg = reinterpret_cast<c32 *>(w + l.gg);
+    b.gs = reinterpret_cast<c32 *>(w + l.gs);
+    b.gt = reinterpret_cast<float *>(w + l.gt);
+    b.grid = gridding;
     const c32 *x = reinterpret_cast<const c32 *>(in);
     c32 *y = reinterpret_cast<c32 *>(out);
     int rc;
@@ -393,8 +627,8 @@ static int nufft_run(int kind, int refine, const double *t, const void *in, void
     const int64_t BP = nblocks * P;
     const unsigned pw_grid = unsigned((BP + NU_PW_TPB - 1) / NU_PW_TPB);
     // residual of the first pass: F y0 - x
-    if (kind == 4) rc = nudft1_launch(t, y, b.t3, nblocks, P, P, s);
-    else rc = nudft2_launch(t, y, b.t3, nblocks, P, P, 0, s);
+    if (kind == 4) rc = sum1(b, t, y, b.t3, nblocks, P, P, stream);
+    else rc = sum2(b, t, y, b.t3, nblocks, P, P, 0, stream);
     if (rc) return rc;
     hipLaunchKernelGGL(nufft_axpy_kernel, dim3(pw_grid), dim3(NU_PW_TPB), 0, s, b.t3, x, -1.f, BP);
     if ((rc = nu_check_launch("nufft residual launch"))) return rc;
@@ -410,8 +644,21 @@ using namespace bt;
 
 extern "C" size_t nufft_workspace_size(int64_t nblocks, int32_t P, int32_t eta)
 {
+    return nufft_workspace_size_ex(nblocks, P, eta, 0);
+}
+
+extern "C" size_t nufft_workspace_size_ex(int64_t nblocks, int32_t P, int32_t eta, int32_t flags)
+{
     if (!nu_shape_ok(P, eta) || !nu_blocks_ok(nblocks)) return 0;
-    return nu_layout(nblocks, P, eta).total;
+    if ((flags & NUFFT_GRIDDING) && !nu_grid_ok(P, eta)) return 0;
+    return nu_layout(nblocks, P, eta, (flags & NUFFT_GRIDDING) != 0).total;
+}
+
+extern "C" int nufft_solve(int32_t type, int32_t flags, const double *t, const void *in, void *out, int64_t nblocks,
+                           int32_t P, int32_t eta, double a, void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (type != 4 && type != 5) return TF_EINVAL;
+    return nufft_run(type, flags, t, in, out, nblocks, P, eta, a, workspace, workspace_bytes, stream);
 }
 
 extern "C" int nufft_type5(const double *t, const void *samples, void *coeffs, int64_t nblocks, int32_t P,
@@ -429,14 +676,62 @@ extern "C" int nufft_type4(const double *t, const void *spectrum, void *amplitud
 extern "C" int nufft_type5_refined(const double *t, const void *samples, void *coeffs, int64_t nblocks, int32_t P,
                                    int32_t eta, double a, void *workspace, size_t workspace_bytes, void *stream)
 {
-    return nufft_run(5, 1, t, samples, coeffs, nblocks, P, eta, a, workspace, workspace_bytes, stream);
+    return nufft_run(5, NUFFT_REFINE, t, samples, coeffs, nblocks, P, eta, a, workspace, workspace_bytes, stream);
 }
 
 extern "C" int nufft_type4_refined(const double *t, const void *spectrum, void *amplitudes, int64_t nblocks,
                                    int32_t P, int32_t eta, double a, void *workspace, size_t workspace_bytes,
                                    void *stream)
 {
-    return nufft_run(4, 1, t, spectrum, amplitudes, nblocks, P, eta, a, workspace, workspace_bytes, stream);
+    return nufft_run(4, NUFFT_REFINE, t, spectrum, amplitudes, nblocks, P, eta, a, workspace, workspace_bytes,
+                     stream);
+}
+
+extern "C" size_t nfft_workspace_size(int64_t nblocks, int32_t band)
+{
+    int n, K, M;
+    if (!nu_blocks_ok(nblocks) || !grid_shape(band, &n, &K, &M)) return 0;
+    return 2 * nu_round(size_t(nblocks) * n * sizeof(c32)) + nu_round(size_t(n) * sizeof(float));
+}
+
+static int nfft_ws(int64_t nblocks, int band, void *ws, size_t ws_bytes, c32 **grid, c32 **spec, float **taps)
+{
+    int n, K, M;
+    if (!grid_shape(band, &n, &K, &M)) return TF_EUNSUPPORTED;
+    const size_t seg = nu_round(size_t(nblocks) * n * sizeof(c32));
+    if (!ws || ws_bytes < nfft_workspace_size(nblocks, band) || !nu_aligned(ws, 256)) return TF_EWORKSPACE;
+    char *w = static_cast<char *>(ws);
+    *grid = reinterpret_cast<c32 *>(w);
+    *spec = reinterpret_cast<c32 *>(w + seg);
+    *taps = reinterpret_cast<float *>(w + 2 * seg);
+    return TF_OK;
+}
+
+extern "C" int nfft_type1(const double *t, const void *amp, void *out, int64_t nblocks, int32_t Q, int32_t R,
+                          void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (Q < 1 || Q > 65536 || !nu_blocks_ok(nblocks)) return TF_EUNSUPPORTED;
+    if (!t || !out || !nu_aligned(t, 8) || !nu_aligned(out, 8) || (amp && !nu_aligned(amp, 8))) return TF_EINVAL;
+    c32 *grid, *spec;
+    float *taps;
+    int rc = nfft_ws(nblocks, R, workspace, workspace_bytes, &grid, &spec, &taps);
+    if (rc) return rc;
+    return grid1_run(t, reinterpret_cast<const c32 *>(amp), reinterpret_cast<c32 *>(out), nblocks, Q, R, grid, spec,
+                     taps, stream);
+}
+
+extern "C" int nfft_type2(const double *t, const void *coeffs, void *out, int64_t nblocks, int32_t P, int32_t Q,
+                          void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (Q < 1 || Q > 65536 || !nu_blocks_ok(nblocks)) return TF_EUNSUPPORTED;
+    if (!t || !coeffs || !out || !nu_aligned(t, 8) || !nu_aligned(coeffs, 8) || !nu_aligned(out, 8))
+        return TF_EINVAL;
+    c32 *grid, *spec;
+    float *taps;
+    int rc = nfft_ws(nblocks, P, workspace, workspace_bytes, &grid, &spec, &taps);
+    if (rc) return rc;
+    return grid2_run(t, reinterpret_cast<const c32 *>(coeffs), reinterpret_cast<c32 *>(out), nblocks, P, Q, 0, grid,
+                     spec, taps, stream);
 }
 
 extern "C" int nudft_type1(const double *t, const void *amp, void *out, int64_t nblocks, int32_t Q, int32_t R,

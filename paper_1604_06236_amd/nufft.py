@@ -38,43 +38,51 @@ def damping_for(mu: float, eta: int, P: int) -> float:
     return -math.log(mu * n) / (2.0 * math.pi * n)
 
 
-def nufft_workspace_size(B: int, P: int, eta: int) -> int:
-    return int(nat.load().nufft_workspace_size(B, P, eta))
+NUFFT_REFINE = 1
+NUFFT_GRIDDING = 2
 
 
-def _solve(fn: str, t: torch.Tensor, x: torch.Tensor, eta: int, a: float, out, workspace):
+def nufft_workspace_size(B: int, P: int, eta: int, flags: int = 0) -> int:
+    return int(nat.load().nufft_workspace_size_ex(B, P, eta, flags))
+
+
+def nufft_solve(kind: int, t: torch.Tensor, x: torch.Tensor, eta: int, a: float, *,
+                refine: bool = False, gridding: bool = False, out: Optional[torch.Tensor] = None,
+                workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """kind 5: coefficients from samples (eq. (48)); kind 4: amplitudes from the
+    spectrum (eq. (47)).  `refine`: the refined method of Sec. 5; `gridding`: the
+    non-uniform sums by gridding NFFTs instead of exact sums."""
     _check(t, "t", torch.float64)
     B, P = t.shape
     _check(x, "input", torch.complex64, (B, P))
     out = torch.empty_like(x) if out is None else out
     _check(out, "out", torch.complex64, (B, P))
-    need = nufft_workspace_size(B, P, eta)
+    flags = (NUFFT_REFINE if refine else 0) | (NUFFT_GRIDDING if gridding else 0)
+    need = nufft_workspace_size(B, P, eta, flags)
     if need == 0:
-        nat.check(fn, nat.TF_EUNSUPPORTED)
+        nat.check("nufft_solve", nat.TF_EUNSUPPORTED)
     if workspace is None:
         workspace = torch.empty(need, dtype=torch.uint8, device=x.device)
     if workspace.numel() < need:
         raise ValueError(f"workspace needs {need} bytes")
-    nat.check(fn, getattr(nat.load(), fn)(
-        _ptr(t), _ptr(x), _ptr(out), B, P, eta, float(a), _ptr(workspace), workspace.numel(),
-        _stream(x.device)))
+    nat.check("nufft_solve", nat.load().nufft_solve(
+        int(kind), flags, _ptr(t), _ptr(x), _ptr(out), B, P, eta, float(a), _ptr(workspace),
+        workspace.numel(), _stream(x.device)))
     return out
 
 
 def nufft_type5(t: torch.Tensor, samples: torch.Tensor, eta: int, a: float, *,
                 out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
-                refine: bool = False):
-    """Coefficients S [B, P] with sum_p S_p e^{j 2 pi p t_q} = samples_q (eq. (48));
-    `refine` runs the refined method of Sec. 5 (eq. (44)-(46))."""
-    return _solve("nufft_type5_refined" if refine else "nufft_type5", t, samples, eta, a, out, workspace)
+                refine: bool = False, gridding: bool = False):
+    """Coefficients S [B, P] with sum_p S_p e^{j 2 pi p t_q} = samples_q (eq. (48))."""
+    return nufft_solve(5, t, samples, eta, a, refine=refine, gridding=gridding, out=out, workspace=workspace)
 
 
 def nufft_type4(t: torch.Tensor, spectrum: torch.Tensor, eta: int, a: float, *,
                 out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
-                refine: bool = False):
-    """Amplitudes a [B, P] with sum_q a_q e^{-j 2 pi r t_q} = spectrum_r, r < P (eq. (47));
-    `refine` runs the refined method of Sec. 5 (eq. (44)-(46))."""
-    return _solve("nufft_type4_refined" if refine else "nufft_type4", t, spectrum, eta, a, out, workspace)
+                refine: bool = False, gridding: bool = False):
+    """Amplitudes a [B, P] with sum_q a_q e^{-j 2 pi r t_q} = spectrum_r, r < P (eq. (47))."""
+    return nufft_solve(4, t, spectrum, eta, a, refine=refine, gridding=gridding, out=out, workspace=workspace)
 
 
 def nudft_type1(t: torch.Tensor, amp: Optional[torch.Tensor], R: int, *,
@@ -104,4 +112,42 @@ def nudft_type2(t: torch.Tensor, coeffs: torch.Tensor, *,
     _check(out, "out", torch.complex64, (B, Q))
     nat.check("nudft_type2", nat.load().nudft_type2(_ptr(t), _ptr(coeffs), _ptr(out), B, P, Q,
                                                     _stream(t.device)))
+    return out
+
+
+def nfft_type1(t: torch.Tensor, amp: Optional[torch.Tensor], R: int, *,
+               out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Gridding type-1 NFFT (Gaussian window, oversampling 2): approximates nudft_type1."""
+    _check(t, "t", torch.float64)
+    B, Q = t.shape
+    if amp is not None:
+        _check(amp, "amp", torch.complex64, (B, Q))
+    out = torch.empty((B, R), dtype=torch.complex64, device=t.device) if out is None else out
+    _check(out, "out", torch.complex64, (B, R))
+    need = int(nat.load().nfft_workspace_size(B, R))
+    if need == 0:
+        nat.check("nfft_type1", nat.TF_EUNSUPPORTED)
+    ws = torch.empty(need, dtype=torch.uint8, device=t.device)
+    nat.check("nfft_type1", nat.load().nfft_type1(_ptr(t), _ptr(amp), _ptr(out), B, Q, R, _ptr(ws), need,
+                                                  _stream(t.device)))
+    return out
+
+
+def nfft_type2(t: torch.Tensor, coeffs: torch.Tensor, *,
+               out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Gridding type-2 NFFT (Gaussian window, oversampling 2): approximates nudft_type2."""
+    _check(t, "t", torch.float64)
+    B, Q = t.shape
+    _check(coeffs, "coeffs", torch.complex64)
+    if coeffs.shape[0] != B:
+        raise ValueError("coeffs must be [B, P]")
+    P = coeffs.shape[1]
+    out = torch.empty((B, Q), dtype=torch.complex64, device=t.device) if out is None else out
+    _check(out, "out", torch.complex64, (B, Q))
+    need = int(nat.load().nfft_workspace_size(B, P))
+    if need == 0:
+        nat.check("nfft_type2", nat.TF_EUNSUPPORTED)
+    ws = torch.empty(need, dtype=torch.uint8, device=t.device)
+    nat.check("nfft_type2", nat.load().nfft_type2(_ptr(t), _ptr(coeffs), _ptr(out), B, P, Q, _ptr(ws), need,
+                                                  _stream(t.device)))
     return out

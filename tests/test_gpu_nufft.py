@@ -183,3 +183,65 @@ def test_refined_rejects_in_place(env):
     P = NU._ptr
     assert lib.nufft_type4_refined(P(t), P(x), P(x), 1, 64, 2, 0.01, P(ws), ws.numel(), None) == nat.TF_EINVAL
     torch.cuda.synchronize()
+
+
+# ------------------------------------------------------------ gridding NFFTs
+@pytest.mark.parametrize("Q,R,unit", [(64, 64, False), (100, 1536, False), (1024, 6144, True), (1024, 2048, False)])
+def test_gridding_type1(env, Q, R, unit):
+    """Gridding type-1 against the gridding oracle and the exact sum; the Gaussian
+    window is set for 1e-7 and the arithmetic is FP32."""
+    from oracle import gridding as G
+    torch, NU, _ = env
+    B = 2
+    t = inst(B, Q, 13 * Q + R)
+    amp = None if unit else cn(np.random.default_rng(R), (B, Q))
+    out = NU.nfft_type1(dev(torch, t), None if unit else dev(torch, amp), R).cpu().numpy()
+    for b in range(B):
+        a_b = np.ones(Q) if unit else amp[b]
+        assert L.rel_err(out[b], G.type1(t[b], a_b, R)) < 2e-6
+        assert L.rel_err(out[b], L.type1(t[b], a_b, R)) < 2e-6
+
+
+@pytest.mark.parametrize("P,Q", [(64, 64), (1024, 1024), (2048, 300)])
+def test_gridding_type2(env, P, Q):
+    from oracle import gridding as G
+    torch, NU, _ = env
+    B = 2
+    t = inst(B, Q, 17 * P + Q)
+    c = cn(np.random.default_rng(P + 1), (B, P))
+    out = NU.nfft_type2(dev(torch, t), dev(torch, c)).cpu().numpy()
+    for b in range(B):
+        assert L.rel_err(out[b], G.type2(c[b], t[b])) < 2e-6
+        assert L.rel_err(out[b], L.type2(c[b], t[b])) < 2e-6
+
+
+@pytest.mark.parametrize("P,eta,mu,refine", [(64, 6, 1e-7, False), (256, 4, 1e-7, False), (1024, 6, 1e-7, False),
+                                             (256, 2, 1e-4, True)])
+def test_methods_with_gridding(env, P, eta, mu, refine):
+    """The type-5 / type-4 methods with every non-uniform sum by gridding, against
+    the FP64 oracle of the methods (exact sums)."""
+    torch, NU, _ = env
+    B = 2
+    a = NU.damping_for(mu, eta, P)
+    t = inst(B, P, 23 * P + eta)
+    rng = np.random.default_rng(P * eta)
+    s = cn(rng, (B, P))
+    A = cn(rng, (B, P))
+    S = NU.nufft_type5(dev(torch, t), dev(torch, s), eta, a, gridding=True, refine=refine).cpu().numpy()
+    x = NU.nufft_type4(dev(torch, t), dev(torch, A), eta, a, gridding=True, refine=refine).cpu().numpy()
+    tol = 2e-5 * amp_of(a, P)
+    f5 = L.type5_refined if refine else L.type5_method
+    f4 = L.type4_refined if refine else L.type4_method
+    for b in range(B):
+        st = L.Setup(t[b], eta, a)
+        assert L.rel_err(S[b], f5(t[b], s[b], eta, a, st)) < tol
+        assert L.rel_err(x[b], f4(t[b], A[b], eta, a, st)) < tol
+
+
+def test_gridding_shape_limits(env):
+    torch, NU, nat = env
+    # 2 eta P = 30720 is not a block-transform size
+    assert NU.nufft_workspace_size(1, 1024, 15, NU.NUFFT_GRIDDING) == 0
+    assert nat.load().nfft_workspace_size(1, 8) == 0
+    assert nat.load().nfft_workspace_size(1, 1000) == 0      # 2000 = 16 x 125
+    assert nat.load().nfft_workspace_size(1, 6144) > 0
