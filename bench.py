@@ -388,27 +388,38 @@ def extras(T, W, args):
     A = torch.from_numpy(A_h).to(dev)
     S5 = torch.empty_like(s)
     a4 = torch.empty_like(A)
-    ws = torch.empty(NU.nufft_workspace_size(B, P, eta), dtype=torch.uint8, device=dev)
-
-    def nstep(i):
-        NU.nufft_type5(tt, s, eta, a, out=S5, workspace=ws)
-        NU.nufft_type4(tt, A, eta, a, out=a4, workspace=ws)
-
-    t = _timeit(nstep, max(3, steps // 10))
-    # exact non-uniform sum terms per step: each method does eta P^2 (eq. (28)) + P^2 (eq. (16))
-    # + P^2 (the weights' type-1 sum, or the type-2 evaluation of s(t_q))
-    terms = 2 * B * (eta + 2) * P * P
     st = LG.Setup(t_h[0], eta, a)
     S_ref = LG.type5_method(t_h[0], s_h[0], eta, a, st)
     a_ref = LG.type4_method(t_h[0], A_h[0], eta, a, st)
-    res["nufft"] = {"solves_per_s": round(2 * B / t, 1), "ms_per_step": round(t * 1e3, 4),
-                    "nudft_terms_per_s": float(f"{terms / t:.4g}"),
-                    "rel_l2_type5_vs_oracle": _rel(S5.cpu().numpy()[0], S_ref),
-                    "rel_l2_type4_vs_oracle": _rel(a4.cpu().numpy()[0], a_ref),
-                    "rel_l2_type5_vs_gaussian_elimination": _rel(S5.cpu().numpy()[0], LG.ge_type5(t_h[0], s_h[0])),
-                    "oracle_method_vs_gaussian_elimination": _rel(S_ref, LG.ge_type5(t_h[0], s_h[0])),
-                    "workload": f"{B} problems of P={P} jittered instants (p/P + U[0, 0.6/P]), eta={eta}, "
-                                f"mu={mu:g} (a={a:.4g}); one type-5 and one type-4 solve each per step"}
+    S_ge = LG.ge_type5(t_h[0], s_h[0])
+    nres = {"workload": f"{B} problems of P={P} jittered instants (p/P + U[0, 0.6/P]), eta={eta}, "
+                        f"mu={mu:g} (a={a:.4g}); one type-5 and one type-4 solve each per step",
+            "oracle_method_vs_gaussian_elimination": _rel(S_ref, S_ge)}
+    for name, refine, gridding in (("exact_sums", False, False), ("gridding", False, True),
+                                   ("exact_sums_refined", True, False)):
+        flags = (NU.NUFFT_REFINE if refine else 0) | (NU.NUFFT_GRIDDING if gridding else 0)
+        ws = torch.empty(NU.nufft_workspace_size(B, P, eta, flags), dtype=torch.uint8, device=dev)
+
+        def nstep(i, refine=refine, gridding=gridding, ws=ws):
+            NU.nufft_type5(tt, s, eta, a, out=S5, workspace=ws, refine=refine, gridding=gridding)
+            NU.nufft_type4(tt, A, eta, a, out=a4, workspace=ws, refine=refine, gridding=gridding)
+
+        t = _timeit(nstep, max(3, steps // 10))
+        e = {"solves_per_s": round(2 * B / t, 1), "ms_per_step": round(t * 1e3, 4)}
+        if not gridding:
+            # exact non-uniform sum terms per step: each method does eta P^2 (eq. (28)) + P^2
+            # (eq. (16)) + P^2 (the weights' type-1 sum, or the type-2 evaluation of s(t_q)),
+            # and the refinement repeats the last P^2 term twice more (residual, second pass)
+            terms = 2 * B * ((eta + 2) * P * P + (2 * P * P if refine else 0))
+            e["nudft_terms_per_s"] = float(f"{terms / t:.4g}")
+        r5 = (LG.type5_refined(t_h[0], s_h[0], eta, a, st) if refine else S_ref)
+        r4 = (LG.type4_refined(t_h[0], A_h[0], eta, a, st) if refine else a_ref)
+        e["rel_l2_type5_vs_oracle"] = _rel(S5.cpu().numpy()[0], r5)
+        e["rel_l2_type4_vs_oracle"] = _rel(a4.cpu().numpy()[0], r4)
+        e["rel_l2_type5_vs_gaussian_elimination"] = _rel(S5.cpu().numpy()[0], S_ge)
+        nres[name] = e
+        del ws
+    res["nufft"] = nres
     return res
 
 
