@@ -10,7 +10,7 @@
 //
 // Numerics.  Instants are turned into 64-bit fixed-point fractions of a cycle,
 // so every phase k t_q mod 1 is formed exactly in integer arithmetic (a 32 x 32
-// high product plus a wrapping multiply-add) before one FP32 sincospi of a
+// high product plus a wrapping multiply-add) before an FP32 sine/cosine of a
 // remainder of at most 1/8 cycle; the sums of such terms accumulate in FP64
 // (MI355X runs FP64 vector FMA at the FP32 rate).  The constant phase
 // P pi + 2 pi sum t of eq. (29) is likewise summed exactly as a fixed-point
@@ -43,20 +43,27 @@ __device__ __forceinline__ uint32_t phase32(uint32_t k, uint32_t tlo, uint32_t t
 }
 
 // exp(+j 2 pi ph / 2^32).  The quadrant is split off exactly in integer
-// arithmetic (nearest multiple of 2^30), so the FP32 argument of sincospi is a
-// remainder of at most 1/8 cycle and keeps 24 significant bits of it.
+// arithmetic (nearest multiple of 2^30), leaving an angle theta of at most
+// pi/4 in magnitude, whose sine and cosine are the Taylor polynomials of
+// degree 9 and 8 (truncation below 2.5e-8, under one FP32 ulp of the result)
+// in Horner form on theta^2.
 __device__ __forceinline__ c32 cis_rev(uint32_t ph)
 {
     const uint32_t quad = (ph + 0x20000000u) >> 30;              // nearest quarter cycle
     const int32_t rem = int32_t(ph - (quad << 30));               // |rem| <= 2^29
-    float s, c;
-    sincospif(float(rem) * 0x1p-31f, &s, &c);                     // rem / 2^32 cycles, times 2
-    switch (quad & 3u) {
-    case 0: return c32{c, s};
-    case 1: return c32{-s, c};
-    case 2: return c32{-c, -s};
-    default: return c32{s, -c};
-    }
+    const float th = float(rem) * 1.4629180792671596e-09f;        // 2 pi / 2^32
+    const float t2 = th * th;
+    const float sp = fmaf(fmaf(fmaf(fmaf(t2, 1.0f / 362880.0f, -1.0f / 5040.0f), t2, 1.0f / 120.0f), t2,
+                               -1.0f / 6.0f), t2, 1.0f);
+    const float s = th * sp;
+    const float c = fmaf(fmaf(fmaf(fmaf(t2, 1.0f / 40320.0f, -1.0f / 720.0f), t2, 1.0f / 24.0f), t2, -0.5f),
+                         t2, 1.0f);
+    // rotate by quad quarter turns without branching: odd quarters swap the
+    // parts, quarters 1 and 2 negate the real part, 2 and 3 the imaginary part
+    const bool odd = quad & 1u;
+    const float x = odd ? s : c, y = odd ? c : s;
+    const uint32_t nx = ((quad + 1u) & 2u) << 30, ny = (quad & 2u) << 30;
+    return c32{__uint_as_float(__float_as_uint(x) ^ nx), __uint_as_float(__float_as_uint(y) ^ ny)};
 }
 
 // ------------------------------------------------------------------ type-1 sums
