@@ -364,8 +364,15 @@ static int nu_check_launch(const char *what)
 static int nudft1_launch(const double *t, const c32 *amp, c32 *out, int64_t nblocks, int Q, int R, hipStream_t s)
 {
     const unsigned gx = unsigned((R + NU1_TPB * NU1_RPT - 1) / (NU1_TPB * NU1_RPT));
-    hipLaunchKernelGGL((nudft1_kernel<NU1_TPB, NU1_RPT>), dim3(gx, unsigned(nblocks)), dim3(NU1_TPB), 0, s, t, amp,
-                       out, Q, R);
+    if (int64_t(gx) * nblocks >= 1024) {
+        hipLaunchKernelGGL((nudft1_kernel<NU1_TPB, NU1_RPT>), dim3(gx, unsigned(nblocks)), dim3(NU1_TPB), 0, s, t,
+                           amp, out, Q, R);
+    } else {
+        // few outputs per problem: one output per thread, so that the grid fills the chip
+        const unsigned g1 = unsigned((R + NU1_TPB - 1) / NU1_TPB);
+        hipLaunchKernelGGL((nudft1_kernel<NU1_TPB, 1>), dim3(g1, unsigned(nblocks)), dim3(NU1_TPB), 0, s, t, amp,
+                           out, Q, R);
+    }
     return nu_check_launch("nudft_type1 launch");
 }
 

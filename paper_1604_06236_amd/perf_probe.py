@@ -21,7 +21,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--what", default="forward",
                     choices=["forward", "adjoint", "forward_adjoint", "ragged", "split_bf16",
-                             "split_fp16", "differentiation", "decimated", "all"])
+                             "split_fp16", "differentiation", "decimated", "nufft", "all"])
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--copy-mib", type=int, default=256)
     ap.add_argument("--config", default=None,
@@ -51,6 +51,20 @@ def main():
 
 def run(what, reps, T, W, np, torch, config=None):
     dev = "cuda"
+    if what == "nufft":
+        from paper_1604_06236_amd import nufft as NU
+        B, P, eta = 256, 1024, 6
+        a = NU.damping_for(1e-7, eta, P)
+        rng = np.random.default_rng(11)
+        t = torch.from_numpy(np.stack([W.jittered_instants(rng, P) for _ in range(B)])).to(dev)
+        s = torch.from_numpy(W.cn01(rng, (B, P)).astype(np.complex64)).to(dev)
+        S = torch.empty_like(s)
+        for _ in range(reps):
+            NU.nufft_type5(t, s, eta, a, out=S)
+            NU.nufft_type5(t, s, eta, a, out=S, gridding=True)
+        torch.cuda.synchronize()
+        print(f"nufft: {reps} x type-5 solves (exact sums, then gridding) on {B} x P={P}, eta={eta}", flush=True)
+        return
     if what == "decimated":
         c = W.CONFIGS["plain_gpu"]
         S_h, taps_h = W.make_uniform(c)
