@@ -235,7 +235,7 @@ int transform_ragged_execute(tf_ragged_plan plan, int32_t direction, const void 
  * eq. (37)).  Shared arguments:
  *   t        in : instants, float64 [nblocks][P], read modulo 1 (the sums are
  *                 1-periodic in t); converted to 64-bit fixed point on the device
- *   nblocks     : problems in the batch, 1..65535
+ *   nblocks     : problems in the batch, 0..65535 (0: nothing is launched)
  *   P           : instants per problem, a power of two in [16, 1024]
  *   eta         : oversampling of eq. (28), R = eta P, 1..16
  *   a           : damping of the shifted grid q/P + ja, > 0; eq. (49) ties it

@@ -598,7 +598,9 @@ static int nufft_run(int kind, int flags, const double *t, const void *in, void 
     const bool refine = flags & NUFFT_REFINE, gridding = flags & NUFFT_GRIDDING;
     if (flags & ~(NUFFT_REFINE | NUFFT_GRIDDING)) return TF_EINVAL;
     if (!nu_shape_ok(P, eta) || (gridding && !nu_grid_ok(P, eta))) return TF_EUNSUPPORTED;
-    if (!nu_blocks_ok(nblocks) || !(a > 0.0) || !std::isfinite(a)) return TF_EINVAL;
+    if (!(a > 0.0) || !std::isfinite(a)) return TF_EINVAL;
+    if (nblocks == 0) return TF_OK;                       // an empty batch is a no-op
+    if (!nu_blocks_ok(nblocks)) return TF_EINVAL;
     if (!t || !in || !out || !nu_aligned(t, 8) || !nu_aligned(in, 8) || !nu_aligned(out, 8)) return TF_EINVAL;
     const NuLayout l = nu_layout(nblocks, P, eta, gridding);
     if (!ws || ws_bytes < l.total || !nu_aligned(ws, 256)) return TF_EWORKSPACE;
@@ -724,7 +726,9 @@ static int nfft_ws(int64_t nblocks, int band, void *ws, size_t ws_bytes, c32 **g
 extern "C" int nfft_type1(const double *t, const void *amp, void *out, int64_t nblocks, int32_t Q, int32_t R,
                           void *workspace, size_t workspace_bytes, void *stream)
 {
-    if (Q < 1 || Q > 65536 || !nu_blocks_ok(nblocks)) return TF_EUNSUPPORTED;
+    if (Q < 1 || Q > 65536) return TF_EUNSUPPORTED;
+    if (nblocks == 0) return TF_OK;
+    if (!nu_blocks_ok(nblocks)) return TF_EUNSUPPORTED;
     if (!t || !out || !nu_aligned(t, 8) || !nu_aligned(out, 8) || (amp && !nu_aligned(amp, 8))) return TF_EINVAL;
     c32 *grid, *spec;
     float *taps;
@@ -737,7 +741,9 @@ extern "C" int nfft_type1(const double *t, const void *amp, void *out, int64_t n
 extern "C" int nfft_type2(const double *t, const void *coeffs, void *out, int64_t nblocks, int32_t P, int32_t Q,
                           void *workspace, size_t workspace_bytes, void *stream)
 {
-    if (Q < 1 || Q > 65536 || !nu_blocks_ok(nblocks)) return TF_EUNSUPPORTED;
+    if (Q < 1 || Q > 65536) return TF_EUNSUPPORTED;
+    if (nblocks == 0) return TF_OK;
+    if (!nu_blocks_ok(nblocks)) return TF_EUNSUPPORTED;
     if (!t || !coeffs || !out || !nu_aligned(t, 8) || !nu_aligned(coeffs, 8) || !nu_aligned(out, 8))
         return TF_EINVAL;
     c32 *grid, *spec;
@@ -751,7 +757,9 @@ extern "C" int nfft_type2(const double *t, const void *coeffs, void *out, int64_
 extern "C" int nudft_type1(const double *t, const void *amp, void *out, int64_t nblocks, int32_t Q, int32_t R,
                            void *stream)
 {
-    if (Q < 1 || Q > NU_MAXP || R < 1 || R > 65536 || !nu_blocks_ok(nblocks)) return TF_EUNSUPPORTED;
+    if (Q < 1 || Q > NU_MAXP || R < 1 || R > 65536) return TF_EUNSUPPORTED;
+    if (nblocks == 0) return TF_OK;
+    if (!nu_blocks_ok(nblocks)) return TF_EUNSUPPORTED;
     if (!t || !out || !nu_aligned(t, 8) || !nu_aligned(out, 8) || (amp && !nu_aligned(amp, 8))) return TF_EINVAL;
     return nudft1_launch(t, reinterpret_cast<const c32 *>(amp), reinterpret_cast<c32 *>(out), nblocks, Q, R,
                          reinterpret_cast<hipStream_t>(stream));
@@ -760,7 +768,9 @@ extern "C" int nudft_type1(const double *t, const void *amp, void *out, int64_t 
 extern "C" int nudft_type2(const double *t, const void *coeffs, void *out, int64_t nblocks, int32_t P, int32_t Q,
                            void *stream)
 {
-    if (P < 1 || P > NU_MAXP || Q < 1 || Q > 65536 || !nu_blocks_ok(nblocks)) return TF_EUNSUPPORTED;
+    if (P < 1 || P > NU_MAXP || Q < 1 || Q > 65536) return TF_EUNSUPPORTED;
+    if (nblocks == 0) return TF_OK;
+    if (!nu_blocks_ok(nblocks)) return TF_EUNSUPPORTED;
     if (!t || !coeffs || !out || !nu_aligned(t, 8) || !nu_aligned(coeffs, 8) || !nu_aligned(out, 8))
         return TF_EINVAL;
     return nudft2_launch(t, reinterpret_cast<const c32 *>(coeffs), reinterpret_cast<c32 *>(out), nblocks, P, Q, 0,

@@ -111,3 +111,36 @@ def test_adjacent_buffers_are_not_overlap(lib):
                                ctypes.c_void_p(1 << 34), ctypes.c_void_p(1 << 36),
                                ctypes.c_void_p(tb - 8), B, K, M, 0, 0, None, 0, None)
     assert rc == nat.TF_EINVAL
+
+
+def test_nufft_host_validation(lib):
+    """Argument checks of the type-4/5 and NFFT entry points, all before any launch."""
+    vp = ctypes.c_void_p
+    t, x, y, ws = vp(1 << 20), vp(1 << 30), vp(1 << 31), vp(1 << 33)
+    big = 1 << 30
+    # empty batches are no-ops
+    assert lib.nufft_type5(None, None, None, 0, 64, 6, 0.01, None, 0, None) == nat.TF_OK
+    assert lib.nufft_solve(4, 3, None, None, None, 0, 64, 2, 0.01, None, 0, None) == nat.TF_OK
+    # shapes
+    assert lib.nufft_type5(t, x, y, 1, 48, 6, 0.01, ws, big, None) == nat.TF_EUNSUPPORTED
+    assert lib.nufft_type5(t, x, y, 1, 2048, 6, 0.01, ws, big, None) == nat.TF_EUNSUPPORTED
+    assert lib.nufft_type4(t, x, y, 1, 64, 0, 0.01, ws, big, None) == nat.TF_EUNSUPPORTED
+    assert lib.nufft_solve(5, 2, t, x, y, 1, 1024, 15, 0.01, ws, big, None) == nat.TF_EUNSUPPORTED
+    # damping, options, type
+    assert lib.nufft_type5(t, x, y, 1, 64, 6, 0.0, ws, big, None) == nat.TF_EINVAL
+    assert lib.nufft_type5(t, x, y, 1, 64, 6, float("nan"), ws, big, None) == nat.TF_EINVAL
+    assert lib.nufft_solve(5, 4, t, x, y, 1, 64, 6, 0.01, ws, big, None) == nat.TF_EINVAL
+    assert lib.nufft_solve(3, 0, t, x, y, 1, 64, 6, 0.01, ws, big, None) == nat.TF_EINVAL
+    # workspace, pointers, overlaps
+    need = lib.nufft_workspace_size(1, 64, 6)
+    assert need > 0 and lib.nufft_workspace_size_ex(1, 64, 6, 2) > need
+    assert lib.nufft_type5(t, x, y, 1, 64, 6, 0.01, ws, need - 1, None) == nat.TF_EWORKSPACE
+    assert lib.nufft_type5(t, x, y, 1, 64, 6, 0.01, vp((1 << 33) + 8), big, None) == nat.TF_EWORKSPACE
+    assert lib.nufft_type5(None, x, y, 1, 64, 6, 0.01, ws, big, None) == nat.TF_EINVAL
+    assert lib.nufft_type4_refined(t, x, x, 1, 64, 6, 0.01, ws, big, None) == nat.TF_EINVAL
+    assert lib.nufft_type5(t, x, ws, 1, 64, 6, 0.01, ws, big, None) == nat.TF_EINVAL
+    # sums
+    assert lib.nudft_type1(t, x, y, 1, 2048, 64, None) == nat.TF_EUNSUPPORTED
+    assert lib.nudft_type2(t, x, y, 1, 64, 0, None) == nat.TF_EUNSUPPORTED
+    assert lib.nfft_workspace_size(1, 1000) == 0 and lib.nfft_workspace_size(1, 6144) > 0
+    assert lib.nfft_type1(t, x, y, 1, 64, 1000, ws, big, None) == nat.TF_EUNSUPPORTED

@@ -245,3 +245,13 @@ def test_gridding_shape_limits(env):
     assert nat.load().nfft_workspace_size(1, 8) == 0
     assert nat.load().nfft_workspace_size(1, 1000) == 0      # 2000 = 16 x 125
     assert nat.load().nfft_workspace_size(1, 6144) > 0
+
+
+def test_empty_batch_is_a_no_op(env):
+    torch, NU, nat = env
+    lib = nat.load()
+    assert lib.nufft_type5(None, None, None, 0, 64, 6, 0.01, None, 0, None) == nat.TF_OK
+    assert lib.nudft_type1(None, None, None, 0, 64, 64, None) == nat.TF_OK
+    assert lib.nudft_type2(None, None, None, 0, 64, 64, None) == nat.TF_OK
+    assert lib.nfft_type1(None, None, None, 0, 64, 64, None, 0, None) == nat.TF_OK
+    torch.cuda.synchronize()
