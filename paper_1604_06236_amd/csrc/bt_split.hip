@@ -115,6 +115,9 @@ struct SplitArgs {
 };
 
 constexpr int ST = 512;   // threads per workgroup (8 waves)
+#ifndef SPLIT_PREFETCH
+#define SPLIT_PREFETCH 0      // holding the next block in registers spills the 32-point stages
+#endif
 
 // k slot -> row index of the 32-wide chunk (see the header comment)
 __device__ __forceinline__ int kperm32(int g, int j) { return j < 4 ? 4 * g + j : 16 + 4 * g + j - 4; }
@@ -165,25 +168,49 @@ __global__ void __launch_bounds__(ST) split_kernel(SplitArgs a)
             fk[t].set(j, a.fk[kr * KS + 16 * t + c]);
         }
 
+    // stage-A operands of one block in registers: each wave owns TPW column tiles;
+    // the next block's are fetched while the current one runs its B stages
+    constexpr int TPW = NT / (ST / 64);
+    static_assert(NT % (ST / 64) == 0, "stage-A tiles must divide among the waves");
+    c32 xin[TPW][4];
+    auto fetch = [&](int64_t bb) {
+        const c32 *inb = a.in + bb * N;
+#pragma unroll
+        for (int i = 0; i < TPW; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int r = 4 * g + j;
+                const int n = 16 * (w + i * (ST / 64)) + c + K * r;
+                xin[i][j] = r < M ? inb[n] : c32{0.f, 0.f};
+            }
+    };
+
     for (int64_t b = blockIdx.x; b < a.nblocks; b += gridDim.x) {
-        const c32 *inb = a.in + b * N;
+        if (!SPLIT_PREFETCH || b == blockIdx.x) fetch(b);
         c32 *outb = a.out + b * N;
         const float *tp = a.taps + b * a.tap_stride;
+        // input-side taps of this block, all issued at once (one latency per block)
+        float tin[SIDE == SIDE_IN ? TPW : 1][SIDE == SIDE_IN ? 4 : 1];
+        if constexpr (SIDE == SIDE_IN) {
+#pragma unroll
+            for (int i = 0; i < TPW; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int r = 4 * g + j;
+                    tin[i][j] = r < M ? tp[16 * (w + i * (ST / 64)) + c + K * r] : 0.f;
+                }
+        }
 
         // ---- stage A: per 16-column tile of p, U = F_M Z, then the coset twiddle
         float sZ = 1.0f;
         if constexpr (P::scaled) {
             float mx = 0.0f;
-            for (int t = w; t < NT; t += ST / 64)
+#pragma unroll
+            for (int i = 0; i < TPW; ++i)
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const int r = 4 * g + j;
-                    if (r < M) {
-                        const int n = 16 * t + c + K * r;
-                        const c32 x = inb[n];
-                        const float f = SIDE == SIDE_IN ? fabsf(tp[n]) : 1.0f;
-                        mx = fmaxf(mx, fmaxf(fabsf(x.x), fabsf(x.y)) * f);
-                    }
+                    const float f = SIDE == SIDE_IN ? fabsf(tin[i][j]) : 1.0f;
+                    mx = fmaxf(mx, fmaxf(fabsf(xin[i][j].x), fabsf(xin[i][j].y)) * f);
                 }
             mx = wave_max(mx);
             __syncthreads();
@@ -195,18 +222,15 @@ __global__ void __launch_bounds__(ST) split_kernel(SplitArgs a)
             sZ = pow2_scale(mx);
         }
         float umax = 0.0f;
-        for (int t = w; t < NT; t += ST / 64) {
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) {
+            const int t = w + i * (ST / 64);
             SplitC<P, 4> z;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int r = 4 * g + j;
-                c32 x = c32{0.f, 0.f};
-                if (r < M) {
-                    const int n = 16 * t + c + K * r;
-                    x = inb[n];
-                    if (conj_io) x = conj(x);
-                    if (SIDE == SIDE_IN) x = scale(x, tp[n]);
-                }
+                c32 x = xin[i][j];
+                if (conj_io) x = conj(x);
+                if constexpr (SIDE == SIDE_IN) x = scale(x, tin[i][j]);
                 z.set(j, scale(x, sZ));
             }
             f4 dr = {0.f, 0.f, 0.f, 0.f}, di = {0.f, 0.f, 0.f, 0.f};
@@ -220,6 +244,8 @@ __global__ void __launch_bounds__(ST) split_kernel(SplitArgs a)
                 if (m < M) umax = fmaxf(umax, fmaxf(fabsf(u.x), fabsf(u.y)));
             }
         }
+        // the next block's stage-A operands, in flight during the B stages
+        if (SPLIT_PREFETCH && b + gridDim.x < a.nblocks) fetch(b + gridDim.x);
         __syncthreads();
         float sU = 1.0f;
         if constexpr (P::scaled) {
@@ -409,7 +435,14 @@ int split_run(int direction, const void *in, const float *taps, void *out, int64
     a.nblocks = nblocks;
     a.tap_stride = tap_stride;
     a.M = M;
-    const unsigned grid = unsigned(std::min<int64_t>(nblocks, 1 << 20));
+    // persistent grid: about two resident rounds of workgroups, so that each
+    // workgroup prefetches its next block while it finishes the current one
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
+    const int per_cu = K == 1024 ? 1 : 2;
+    const unsigned grid = unsigned(std::min<int64_t>(nblocks, int64_t(cus) * per_cu));
     const int side = direction == 0 ? SIDE_IN : SIDE_OUT;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipError_t e;
