@@ -41,9 +41,8 @@ struct RaggedArgs {
     const c32 *aux;
     float *tapbar;
     int *status;
-    const int64_t *x_off;     // per block (original numbering)
+    const int64_t *x_off;     // per block, in the plan's order (sorted by class and cost)
     const int64_t *tap_off;
-    const int *order;         // blocks sorted by class and cost
     const RaggedItem *items;
     const c32 *tw;            // concatenated base-root tables of the classes
     const int *tw_off;        // per class
@@ -52,7 +51,7 @@ struct RaggedArgs {
     int div;
 };
 
-// Chunk body of one class: `it.count` blocks (order[it.first ...]) processed as
+// Chunk body of one class: `it.count` blocks (plan entries it.first ...) processed as
 // tiles of up to BPW blocks, TB threads per block (TB >= 64, so a wave never
 // straddles two blocks and block bases are wave-uniform).  With PF the next
 // tile's inputs are fetched while the current one runs its LDS passes.
@@ -113,10 +112,10 @@ __device__ __forceinline__ void ragged_chunk(const RaggedArgs &a, const RaggedIt
         Res r;
         const int slot = t * BPW + bi;
         r.valid = slot < it.count;
-        int blk = r.valid ? a.order[it.first + slot] : 0;
-        blk = __builtin_amdgcn_readfirstlane(blk);
-        const int64_t xo = a.x_off[blk];
-        const int64_t to = a.tap_off[blk];
+        int e = r.valid ? it.first + slot : 0;
+        e = __builtin_amdgcn_readfirstlane(e);
+        const int64_t xo = a.x_off[e];
+        const int64_t to = a.tap_off[e];
         const uint32_t nb = r.valid ? N : 0;
         r.in = make_rsrc(a.in + xo, nb * CB);
         r.out = make_rsrc(a.out + xo, nb * CB);
@@ -387,8 +386,7 @@ struct tf_ragged_plan_s {
     int nitems = 0;
     int max_lds = 0;
     int grid[3] = {0, 0, 0};
-    int64_t *x_off = nullptr, *tap_off = nullptr;
-    int *order = nullptr;
+    int64_t *x_off = nullptr, *tap_off = nullptr;   // in plan order
     bt::RaggedItem *items = nullptr;
     bt::c32 *tw = nullptr;
     int *tw_off = nullptr;
@@ -412,7 +410,6 @@ static void plan_free(tf_ragged_plan p)
     for (auto &kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
     (void)hipFree(p->x_off);
     (void)hipFree(p->tap_off);
-    (void)hipFree(p->order);
     (void)hipFree(p->items);
     (void)hipFree(p->tw);
     (void)hipFree(p->tw_off);
@@ -535,11 +532,15 @@ extern "C" int transform_ragged_plan_create_ex(const int32_t *K, const int32_t *
     p->nblocks = nblocks;
     p->nitems = int(sorted.size());
     p->max_lds = max_lds;
-    std::vector<int64_t> xo(x_off, x_off + nblocks), to(tap_off, tap_off + nblocks);
+    // offsets in plan order: a tile's block address is one load away from its entry
+    std::vector<int64_t> xo(order.size()), to(order.size());
+    for (size_t e = 0; e < order.size(); ++e) {
+        xo[e] = x_off[order[e]];
+        to[e] = tap_off[order[e]];
+    }
     int rc = TF_OK;
     if (!rc) rc = upload_vec(xo, &p->x_off);
     if (!rc) rc = upload_vec(to, &p->tap_off);
-    if (!rc) rc = upload_vec(order, &p->order);
     if (!rc) rc = upload_vec(sorted, &p->items);
     if (!rc) rc = upload_vec(tw, &p->tw);
     if (!rc) rc = upload_vec(tw_off, &p->tw_off);
@@ -617,7 +618,6 @@ extern "C" int transform_ragged_execute(tf_ragged_plan plan, int32_t direction, 
     a.status = status_dev;
     a.x_off = plan->x_off;
     a.tap_off = plan->tap_off;
-    a.order = plan->order;
     a.items = plan->items;
     a.tw = plan->tw;
     a.tw_off = plan->tw_off;
