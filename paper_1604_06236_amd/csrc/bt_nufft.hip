@@ -236,37 +236,67 @@ __global__ void nufft_axpy_kernel(c32 *y, const c32 *x, float alpha, int64_t tot
 constexpr int GRID_HALF = 8;                         // ceil(sqrt(2) ln(1e7) / pi)
 constexpr double GRID_LOG_INV_EPS = 16.11809565095832;   // ln(1e7)
 
-// spread the (modulated) amplitudes of one problem onto its fine grid in LDS
-// (float atomics), then store the grid.  One workgroup per problem; dynamic
-// LDS of 2 n floats.
+// spread the (modulated) amplitudes of one problem onto its fine grid, then store
+// the grid.  One workgroup per problem.  The accumulation is in 64-bit fixed
+// point with LDS integer atomics (the float LDS atomics of this chip are several
+// times slower, and integer sums are exact and order-independent): every
+// product c w is a float whose scaling by 2^S is exact, with 2^S chosen from the
+// largest amplitude so that Q max|a| 2^S < 2^62; each sum is rounded once, when
+// it is converted back to FP32.  Real and imaginary parts take one pass each, so
+// the LDS grid is n 64-bit words (dynamic LDS).
 template <int TPB>
 __global__ void __launch_bounds__(TPB) grid_spread_kernel(const double *t, const c32 *amp, c32 *grid, int Q, int n,
                                                           int rhalf, float kappa)
 {
-    extern __shared__ float g_lds[];
+    extern __shared__ unsigned long long g_acc[];
+    __shared__ float s_max[TPB / 64];
     const int64_t b = blockIdx.x;
-    for (int i = threadIdx.x; i < 2 * n; i += TPB) g_lds[i] = 0.f;
-    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+
+    // scale: the modulation has unit magnitude, so |Re c|, |Im c| <= |a|
+    float mx = 0.f;
     for (int q = threadIdx.x; q < Q; q += TPB) {
-        const uint64_t T = fixed_instant(t[b * Q + q]);
         const c32 a = amp ? amp[b * Q + q] : c32{1.f, 0.f};
-        const c32 e = cis_rev(0u - phase32(uint32_t(rhalf), uint32_t(T), uint32_t(T >> 32)));
-        const c32 c = c32{a.x * e.x - a.y * e.y, a.x * e.y + a.y * e.x};
-        const double x = double(T >> 11) * 0x1p-53 * double(n);        // n t in [0, n)
-        const double fl = floor(x);
-        const int m0 = min(int(fl), n - 1);
-        const float fx = float(x - fl);
-        for (int j = -GRID_HALF + 1; j <= GRID_HALF; ++j) {
-            int m = m0 + j;
-            m = m < 0 ? m + n : (m >= n ? m - n : m);
-            const float d = fx - float(j);
-            const float w = __expf(-kappa * d * d);
-            atomicAdd(&g_lds[2 * m], c.x * w);
-            atomicAdd(&g_lds[2 * m + 1], c.y * w);
-        }
+        mx = fmaxf(mx, fmaxf(fabsf(a.x), fabsf(a.y)));
     }
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+    if (lane == 0) s_max[wv] = mx;
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += TPB) grid[b * n + i] = c32{g_lds[2 * i], g_lds[2 * i + 1]};
+    mx = 0.f;
+#pragma unroll
+    for (int i = 0; i < TPB / 64; ++i) mx = fmaxf(mx, s_max[i]);
+    int e_a = 0, e_q = 0;
+    frexpf(mx, &e_a);                            // mx < 2^e_a
+    frexpf(float(Q), &e_q);                      // Q < 2^e_q (or equal: then 2^e_q > Q)
+    const int S = mx > 0.f ? 62 - e_a - e_q : 0;
+    const float up = ldexpf(1.0f, S), down = ldexpf(1.0f, -S);
+
+    float *gf = reinterpret_cast<float *>(grid + b * n);
+    for (int comp = 0; comp < 2; ++comp) {
+        for (int i = threadIdx.x; i < n; i += TPB) g_acc[i] = 0ull;
+        __syncthreads();
+        for (int q = threadIdx.x; q < Q; q += TPB) {
+            const uint64_t T = fixed_instant(t[b * Q + q]);
+            const c32 a = amp ? amp[b * Q + q] : c32{1.f, 0.f};
+            const c32 e = cis_rev(0u - phase32(uint32_t(rhalf), uint32_t(T), uint32_t(T >> 32)));
+            const float cv = comp == 0 ? a.x * e.x - a.y * e.y : a.x * e.y + a.y * e.x;
+            const double x = double(T >> 11) * 0x1p-53 * double(n);        // n t in [0, n)
+            const double fl = floor(x);
+            const int m0 = min(int(fl), n - 1);
+            const float fx = float(x - fl);
+            for (int j = -GRID_HALF + 1; j <= GRID_HALF; ++j) {
+                int m = m0 + j;
+                m = m < 0 ? m + n : (m >= n ? m - n : m);
+                const float d = fx - float(j);
+                const float w = __expf(-kappa * d * d);
+                const long long v = (long long)((cv * w) * up);           // exact: a power-of-two scaling
+                atomicAdd(&g_acc[m], (unsigned long long)v);
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += TPB) gf[2 * i + comp] = float((long long)g_acc[i]) * down;
+        __syncthreads();
+    }
 }
 
 // deconvolution taps over the n bins of the fine grid: for the bins of the
