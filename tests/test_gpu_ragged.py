@@ -142,3 +142,17 @@ def test_ragged_plan_rejects_bad_layouts(T):
         T.RaggedPlan([48], [3], [0], [0], 144)          # K not a power of two
     with pytest.raises(TransformError):
         T.RaggedPlan([64], [3], [100], [0], 200)        # block runs past the end
+
+
+def test_ragged_chunk_sizes_agree(T):
+    """Work-item sizes only change which workgroup runs a tile, never the arithmetic:
+    every chunking gives bit-identical results."""
+    lay, S, taps = W.make_ragged("ragged", nblocks=400)
+    dS, dt = _dev(S), _dev(taps)
+    outs = []
+    for chunk in (1, 3, 4, 16):
+        plan = T.RaggedPlan(lay.K, lay.M, lay.x_off, lay.tap_off, lay.total, chunk_tiles=chunk)
+        outs.append(_host(plan.execute("forward", dS, dt, use_graph=False)))
+        plan.close()
+    for o in outs[1:]:
+        assert np.array_equal(o.view(np.uint64), outs[0].view(np.uint64))
