@@ -107,6 +107,119 @@ __global__ void __launch_bounds__(TPB) nudft1_kernel(const double *t, const c32 
     }
 }
 
+// exp(+j 2 pi ph / 2^64) in FP64: quadrant split off exactly in integers, the
+// remainder (at most pi/4) through Taylor polynomials of degree 17 / 16, whose
+// truncation is below 1e-17
+struct d2 {
+    double x, y;
+};
+
+__device__ __forceinline__ d2 cis_rev64(uint64_t ph)
+{
+    const uint64_t quad = (ph + (uint64_t(1) << 61)) >> 62;
+    const int64_t rem = int64_t(ph - (quad << 62));                    // |rem| <= 2^61
+    const double th = double(rem) * 3.4061215800865545e-19;             // 2 pi / 2^64
+    const double t2 = th * th;
+    double sp = 1.0 / 355687428096000.0;                                // 1/17!
+    sp = fma(sp, t2, -1.0 / 1307674368000.0);                           // 1/15!
+    sp = fma(sp, t2, 1.0 / 6227020800.0);
+    sp = fma(sp, t2, -1.0 / 39916800.0);
+    sp = fma(sp, t2, 1.0 / 362880.0);
+    sp = fma(sp, t2, -1.0 / 5040.0);
+    sp = fma(sp, t2, 1.0 / 120.0);
+    sp = fma(sp, t2, -1.0 / 6.0);
+    const double sn = th * fma(sp, t2, 1.0);
+    double cp = 1.0 / 20922789888000.0;                                 // 1/16!
+    cp = fma(cp, t2, -1.0 / 87178291200.0);
+    cp = fma(cp, t2, 1.0 / 479001600.0);
+    cp = fma(cp, t2, -1.0 / 3628800.0);
+    cp = fma(cp, t2, 1.0 / 40320.0);
+    cp = fma(cp, t2, -1.0 / 720.0);
+    cp = fma(cp, t2, 1.0 / 24.0);
+    cp = fma(cp, t2, -0.5);
+    const double cs = fma(cp, t2, 1.0);
+    const bool odd = quad & 1u;
+    const double x = odd ? sn : cs, y = odd ? cs : sn;
+    const bool nx = (quad + 1u) & 2u, ny = quad & 2u;
+    return d2{nx ? -x : x, ny ? -y : y};
+}
+
+typedef double dd4 __attribute__((ext_vector_type(4)));
+
+// Type-1 sum as a complex matrix product on the FP64 matrix cores.  With
+// r = r1 + 64 r2,  A(r) = sum_q U[r1][q] V[q][r2],  U[r1][q] = a_q e^{-j 2 pi r1 t_q},
+// V[q][r2] = e^{-j 2 pi 64 r2 t_q}: the O(Q R) phase evaluations of the direct sum
+// become O(Q (64 + R/64)) table entries (exact 64-bit fixed-point phases, FP64
+// sine/cosine) and the sum itself runs as v_mfma_f64_16x16x4 (lane l: A[l%16][l/16],
+// B[l/16][l%16], D[4j + l/16][l%16]).  One workgroup per (problem, 16 CT columns of
+// r2); wave w owns the rows r1 in [16 w, 16 w + 16).
+template <int CT>
+__global__ void __launch_bounds__(256) nudft1_mfma_kernel(const double *t, const c32 *amp, c32 *out, int Q, int R)
+{
+    constexpr int QC = 16;                           // instants per staged chunk
+    constexpr int NC = 16 * CT;                      // r2 columns of this workgroup
+    __shared__ double Ur[64][QC + 1], Ui[64][QC + 1];
+    __shared__ double Vr[QC][NC + 1], Vi[QC][NC + 1];
+    __shared__ uint64_t sT[QC];
+    __shared__ c32 sA[QC];
+    const int64_t b = blockIdx.y;
+    const int R2 = R / 64;
+    const int c0 = blockIdx.x * NC;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    dd4 dr[CT], di[CT];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) dr[ct] = di[ct] = dd4{0.0, 0.0, 0.0, 0.0};
+
+    for (int q0 = 0; q0 < Q; q0 += QC) {
+        if (threadIdx.x < QC) {
+            const int q = q0 + threadIdx.x;
+            sT[threadIdx.x] = q < Q ? fixed_instant(t[b * Q + q]) : 0;
+            sA[threadIdx.x] = q < Q ? (amp ? amp[b * Q + q] : c32{1.f, 0.f}) : c32{0.f, 0.f};
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < 64 * QC; e += 256) {
+            const int r1 = e / QC, qq = e - (e / QC) * QC;
+            const d2 c = cis_rev64(uint64_t(0) - uint64_t(r1) * sT[qq]);       // e^{-j 2 pi r1 t}
+            const double ax = sA[qq].x, ay = sA[qq].y;
+            Ur[r1][qq] = ax * c.x - ay * c.y;
+            Ui[r1][qq] = ax * c.y + ay * c.x;
+        }
+        for (int e = threadIdx.x; e < QC * NC; e += 256) {
+            const int qq = e / NC, j = e - (e / NC) * NC;
+            const int r2 = c0 + j;
+            d2 c = d2{0.0, 0.0};
+            if (r2 < R2 && q0 + qq < Q) c = cis_rev64(uint64_t(0) - uint64_t(64 * r2) * sT[qq]);
+            Vr[qq][j] = c.x;
+            Vi[qq][j] = c.y;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s4 = 0; s4 < QC / 4; ++s4) {
+            const int kq = 4 * s4 + (l >> 4);
+            const double ar = Ur[16 * w + (l & 15)][kq], ai = Ui[16 * w + (l & 15)][kq];
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+                const double br = Vr[kq][16 * ct + (l & 15)], bi = Vi[kq][16 * ct + (l & 15)];
+                dr[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, dr[ct], 0, 0, 0);
+                dr[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, bi, dr[ct], 0, 0, 0);
+                di[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, di[ct], 0, 0, 0);
+                di[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, di[ct], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+        const int r2 = c0 + 16 * ct + (l & 15);
+        if (r2 >= R2) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int r1 = 16 * w + 4 * j + (l >> 4);
+            out[b * R + r1 + 64 * r2] = c32{float(dr[ct][j]), float(di[ct][j])};
+        }
+    }
+}
+
 // ------------------------------------------------------------------ type-2 sums
 // out[b][q] = sum_{p<P} c_p exp(+j 2 pi p t[b][q]),  q < Q  (eq. (34)).
 // deriv == 0: c_p = coef[b][p].  deriv == 1: the coefficients of L'(z) from the
@@ -393,6 +506,19 @@ static int nu_check_launch(const char *what)
 
 static int nudft1_launch(const double *t, const c32 *amp, c32 *out, int64_t nblocks, int Q, int R, hipStream_t s)
 {
+    if (R % 64 == 0) {
+        // matrix-core form; three column tiles per workgroup when the grid still fills the chip
+        const int R2 = R / 64;
+        const int64_t g3 = (R2 + 47) / 48;
+        if (R2 >= 48 && g3 * nblocks >= 512) {
+            hipLaunchKernelGGL((nudft1_mfma_kernel<3>), dim3(unsigned(g3), unsigned(nblocks)), dim3(256), 0, s, t, amp,
+                               out, Q, R);
+        } else {
+            hipLaunchKernelGGL((nudft1_mfma_kernel<1>), dim3(unsigned((R2 + 15) / 16), unsigned(nblocks)), dim3(256), 0,
+                               s, t, amp, out, Q, R);
+        }
+        return nu_check_launch("nudft_type1 launch");
+    }
     const unsigned gx = unsigned((R + NU1_TPB * NU1_RPT - 1) / (NU1_TPB * NU1_RPT));
     if (int64_t(gx) * nblocks >= 1024) {
         hipLaunchKernelGGL((nudft1_kernel<NU1_TPB, NU1_RPT>), dim3(gx, unsigned(nblocks)), dim3(NU1_TPB), 0, s, t,
