@@ -9,10 +9,11 @@
 // eq. (8), eq. (37) is the forward with the same taps (M = 1).
 //
 // Numerics.  Instants are turned into 64-bit fixed-point fractions of a cycle,
-// so every phase k t_q mod 1 is formed exactly in integer arithmetic (a 32 x 32
-// high product plus a wrapping multiply-add) before an FP32 sine/cosine of a
-// remainder of at most 1/8 cycle; the sums of such terms accumulate in FP64
-// (MI355X runs FP64 vector FMA at the FP32 rate).  The constant phase
+// so every phase k t_q mod 1 is formed exactly in integer arithmetic before the
+// sine/cosine of a remainder of at most 1/8 cycle.  Where the frequency count is
+// a multiple of 64 the sums are complex matrix products on the FP64 matrix cores
+// over tables of such exponentials (FP64 sine/cosine); otherwise each term is an
+// FP32 sine/cosine and the terms accumulate in FP64.  The constant phase
 // P pi + 2 pi sum t of eq. (29) is likewise summed exactly as a fixed-point
 // fraction.  Everything else is FP32.
 #include <hip/hip_runtime.h>
@@ -144,78 +145,146 @@ __device__ __forceinline__ d2 cis_rev64(uint64_t ph)
     return d2{nx ? -x : x, ny ? -y : y};
 }
 
+__device__ __forceinline__ d2 cmul64(d2 a, d2 b) { return d2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+
 typedef double dd4 __attribute__((ext_vector_type(4)));
 
-// Type-1 sum as a complex matrix product on the FP64 matrix cores.  With
-// r = r1 + 64 r2,  A(r) = sum_q U[r1][q] V[q][r2],  U[r1][q] = a_q e^{-j 2 pi r1 t_q},
+// Complex products on the FP64 matrix cores, three real products per complex one
+// (Gauss): with the A tile stored as (re, im, re + im) and the B tile as
+// (re, im - re, re + im),  T1 = (Ar + Ai) Br,  T2 = Ar (Bi - Br),  T3 = Ai (Br + Bi),
+// re = T1 - T3,  im = T1 + T2.  v_mfma_f64_16x16x4 operand layout (lane l):
+// A[l % 16][l / 16], B[l / 16][l % 16], result element j at D[4 j + l / 16][l % 16].
+struct cacc {
+    dd4 t1, t2, t3;
+};
+
+__device__ __forceinline__ void cmfma(cacc &d, double as, double ar, double ai, double br, double bd, double bs)
+{
+    d.t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(as, br, d.t1, 0, 0, 0);
+    d.t2 = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bd, d.t2, 0, 0, 0);
+    d.t3 = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bs, d.t3, 0, 0, 0);
+}
+
+constexpr int NU_QC = 16;    // contraction depth staged per step of the matrix-core sums
+
+// Type-1 sum as a complex matrix product.  With r = r1 + 64 r2,
+// A(r) = sum_q U[r1][q] V[q][r2],  U[r1][q] = a_q e^{-j 2 pi r1 t_q},
 // V[q][r2] = e^{-j 2 pi 64 r2 t_q}: the O(Q R) phase evaluations of the direct sum
 // become O(Q (64 + R/64)) table entries (exact 64-bit fixed-point phases, FP64
-// sine/cosine) and the sum itself runs as v_mfma_f64_16x16x4 (lane l: A[l%16][l/16],
-// B[l/16][l%16], D[4j + l/16][l%16]).  One workgroup per (problem, 16 CT columns of
-// r2); wave w owns the rows r1 in [16 w, 16 w + 16).
-template <int CT>
-__global__ void __launch_bounds__(256) nudft1_mfma_kernel(const double *t, const c32 *amp, c32 *out, int Q, int R)
+// sine/cosine) and the sum itself runs on the matrix cores.  One workgroup per
+// (problem, 16 CT columns of r2) with G groups of four waves; group g takes every
+// G-th chunk of 16 instants (more waves per CU when a problem has few columns), and
+// the groups' partial sums are added through LDS at the end.  Wave w of a group owns
+// the rows r1 in [16 w, 16 w + 16).
+template <int CT, int G>
+struct Nu1Smem {
+    static constexpr int NC = 16 * CT;
+    struct Tab {
+        double u[3][64][NU_QC + 1];     // a e^{-j 2 pi r1 t}: re, im, re + im
+        double v[3][NU_QC][NC + 1];     // e^{-j 2 pi 64 r2 t}: re, im - re, re + im
+        uint64_t T[NU_QC];
+        c32 a[NU_QC];
+    };
+    union {
+        Tab tab[G];
+        double red[G > 1 ? G - 1 : 1][4][CT][2][4][64];
+    };
+};
+
+template <int CT, int G>
+__global__ void __launch_bounds__(256 * G) nudft1_mfma_kernel(const double *t, const c32 *amp, c32 *out, int Q, int R)
 {
-    constexpr int QC = 16;                           // instants per staged chunk
-    constexpr int NC = 16 * CT;                      // r2 columns of this workgroup
-    __shared__ double Ur[64][QC + 1], Ui[64][QC + 1];
-    __shared__ double Vr[QC][NC + 1], Vi[QC][NC + 1];
-    __shared__ uint64_t sT[QC];
-    __shared__ c32 sA[QC];
+    constexpr int NC = 16 * CT;
+    __shared__ Nu1Smem<CT, G> sm;
     const int64_t b = blockIdx.y;
     const int R2 = R / 64;
     const int c0 = blockIdx.x * NC;
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    dd4 dr[CT], di[CT];
+    const int g = threadIdx.x >> 8, tx = threadIdx.x & 255;
+    const int w = tx >> 6, l = tx & 63;
+    auto &tb = sm.tab[g];
+    cacc acc[CT];
 #pragma unroll
-    for (int ct = 0; ct < CT; ++ct) dr[ct] = di[ct] = dd4{0.0, 0.0, 0.0, 0.0};
+    for (int ct = 0; ct < CT; ++ct) acc[ct].t1 = acc[ct].t2 = acc[ct].t3 = dd4{0.0, 0.0, 0.0, 0.0};
 
-    for (int q0 = 0; q0 < Q; q0 += QC) {
-        if (threadIdx.x < QC) {
-            const int q = q0 + threadIdx.x;
-            sT[threadIdx.x] = q < Q ? fixed_instant(t[b * Q + q]) : 0;
-            sA[threadIdx.x] = q < Q ? (amp ? amp[b * Q + q] : c32{1.f, 0.f}) : c32{0.f, 0.f};
+    const int nit = (Q + G * NU_QC - 1) / (G * NU_QC);      // the same trip count for every group
+    for (int it = 0; it < nit; ++it) {
+        const int q0 = (it * G + g) * NU_QC;
+        if (tx < NU_QC) {
+            const int q = q0 + tx;
+            tb.T[tx] = q < Q ? fixed_instant(t[b * Q + q]) : 0;
+            tb.a[tx] = q < Q ? (amp ? amp[b * Q + q] : c32{1.f, 0.f}) : c32{0.f, 0.f};
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < 64 * QC; e += 256) {
-            const int r1 = e / QC, qq = e - (e / QC) * QC;
-            const d2 c = cis_rev64(uint64_t(0) - uint64_t(r1) * sT[qq]);       // e^{-j 2 pi r1 t}
-            const double ax = sA[qq].x, ay = sA[qq].y;
-            Ur[r1][qq] = ax * c.x - ay * c.y;
-            Ui[r1][qq] = ax * c.y + ay * c.x;
-        }
-        for (int e = threadIdx.x; e < QC * NC; e += 256) {
-            const int qq = e / NC, j = e - (e / NC) * NC;
-            const int r2 = c0 + j;
-            d2 c = d2{0.0, 0.0};
-            if (r2 < R2 && q0 + qq < Q) c = cis_rev64(uint64_t(0) - uint64_t(64 * r2) * sT[qq]);
-            Vr[qq][j] = c.x;
-            Vi[qq][j] = c.y;
+        {
+            // thread (qq, i0): rows r1 = i0 + 16 i and columns j = i0 + 16 i, each run from
+            // one exponential and its step e^{-j 2 pi 16 r t}
+            const int qq = tx & 15, i0 = tx >> 4;
+            const uint64_t T = tb.T[qq];
+            const double ax = tb.a[qq].x, ay = tb.a[qq].y;
+            d2 c = cis_rev64(uint64_t(0) - uint64_t(i0) * T);                    // e^{-j 2 pi r1 t}
+            c = d2{ax * c.x - ay * c.y, ax * c.y + ay * c.x};
+            const d2 st = cis_rev64(uint64_t(0) - uint64_t(16) * T);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r1 = i0 + 16 * i;
+                tb.u[0][r1][qq] = c.x;
+                tb.u[1][r1][qq] = c.y;
+                tb.u[2][r1][qq] = c.x + c.y;
+                c = cmul64(c, st);
+            }
+            const bool live = q0 + qq < Q;
+            d2 v = cis_rev64(uint64_t(0) - uint64_t(64 * (c0 + i0)) * T);         // e^{-j 2 pi 64 r2 t}
+            const d2 sv = CT > 1 ? cis_rev64(uint64_t(0) - uint64_t(64 * 16) * T) : d2{1.0, 0.0};
+#pragma unroll
+            for (int i = 0; i < CT; ++i) {
+                const int j = i0 + 16 * i;
+                const d2 c2 = (live && c0 + j < R2) ? v : d2{0.0, 0.0};
+                tb.v[0][qq][j] = c2.x;
+                tb.v[1][qq][j] = c2.y - c2.x;
+                tb.v[2][qq][j] = c2.x + c2.y;
+                if (i + 1 < CT) v = cmul64(v, sv);
+            }
         }
         __syncthreads();
 #pragma unroll
-        for (int s4 = 0; s4 < QC / 4; ++s4) {
-            const int kq = 4 * s4 + (l >> 4);
-            const double ar = Ur[16 * w + (l & 15)][kq], ai = Ui[16 * w + (l & 15)][kq];
+        for (int s4 = 0; s4 < NU_QC / 4; ++s4) {
+            const int kq = 4 * s4 + (l >> 4), row = 16 * w + (l & 15);
+            const double ar = tb.u[0][row][kq], ai = tb.u[1][row][kq], as = tb.u[2][row][kq];
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
-                const double br = Vr[kq][16 * ct + (l & 15)], bi = Vi[kq][16 * ct + (l & 15)];
-                dr[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, dr[ct], 0, 0, 0);
-                dr[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, bi, dr[ct], 0, 0, 0);
-                di[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, di[ct], 0, 0, 0);
-                di[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, di[ct], 0, 0, 0);
+                const int col = 16 * ct + (l & 15);
+                cmfma(acc[ct], as, ar, ai, tb.v[0][kq][col], tb.v[1][kq][col], tb.v[2][kq][col]);
             }
         }
         __syncthreads();
     }
+    if constexpr (G > 1) {
+        // the tables are dead (last barrier above): reuse their LDS for the group sums
+        if (g > 0) {
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    sm.red[g - 1][w][ct][0][j][l] = acc[ct].t1[j] - acc[ct].t3[j];
+                    sm.red[g - 1][w][ct][1][j][l] = acc[ct].t1[j] + acc[ct].t2[j];
+                }
+        }
+        __syncthreads();
+        if (g > 0) return;
+    }
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
         const int r2 = c0 + 16 * ct + (l & 15);
-        if (r2 >= R2) continue;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
+            double re = acc[ct].t1[j] - acc[ct].t3[j], im = acc[ct].t1[j] + acc[ct].t2[j];
+#pragma unroll
+            for (int h = 0; h + 1 < G; ++h) {
+                re += sm.red[h][w][ct][0][j][l];
+                im += sm.red[h][w][ct][1][j][l];
+            }
             const int r1 = 16 * w + 4 * j + (l >> 4);
-            out[b * R + r1 + 64 * r2] = c32{float(dr[ct][j]), float(di[ct][j])};
+            if (r2 < R2) out[b * R + r1 + 64 * r2] = c32{float(re), float(im)};
         }
     }
 }
@@ -257,6 +326,113 @@ __global__ void __launch_bounds__(TPB) nudft2_kernel(const double *t, const c32 
         ay = fma(cx, ey, fma(cy, ex, ay));
     }
     out[b * Q + q] = c32{float(ax), float(ay)};
+}
+
+// Type-2 sum on the matrix cores.  With p = p1 + 64 p2,
+// s(t_q) = sum_{p1<64} e^{j 2 pi p1 t_q} W[p1][q],  W[p1][q] = sum_{p2} C[p1][p2] V[p2][q],
+// C[p1][p2] = c_{p1 + 64 p2},  V[p2][q] = e^{j 2 pi 64 p2 t_q}:  W is a complex matrix
+// product over P/64 terms (16 per staged step, zero-padded), the outer sum a
+// pointwise product with a 64-row reduction.  One workgroup of four waves per
+// (problem, 16 CT instants); wave w owns the rows p1 in [16 w, 16 w + 16).
+// Coefficients as in the direct kernel (deriv: those of L', eq. (16)).
+template <int CT>
+__global__ void __launch_bounds__(256) nudft2_mfma_kernel(const double *t, const c32 *coef, c32 *out, int P, int Q,
+                                                         int deriv)
+{
+    constexpr int NC = 16 * CT;
+    __shared__ double cu[3][64][NU_QC + 1];     // C: re, im, re + im
+    __shared__ double vb[3][NU_QC][NC + 1];     // V: re, im - re, re + im
+    __shared__ uint64_t sT[NC];
+    __shared__ double red[2][4][NC];
+    const int64_t b = blockIdx.y;
+    const int P2 = P / 64;
+    const int c0 = blockIdx.x * NC;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (threadIdx.x < NC) {
+        const int q = c0 + threadIdx.x;
+        sT[threadIdx.x] = q < Q ? fixed_instant(t[b * Q + q]) : 0;
+    }
+    cacc acc[CT];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) acc[ct].t1 = acc[ct].t2 = acc[ct].t3 = dd4{0.0, 0.0, 0.0, 0.0};
+    __syncthreads();
+    for (int k0 = 0; k0 < P2; k0 += NU_QC) {
+        for (int e = threadIdx.x; e < 64 * NU_QC; e += 256) {
+            const int kk = e / 64, p1 = e % 64;          // consecutive threads: consecutive coefficients
+            const int p = p1 + 64 * (k0 + kk);
+            double cr = 0.0, ci = 0.0;
+            if (k0 + kk < P2) {
+                if (!deriv) {
+                    const c32 c = coef[b * P + p];
+                    cr = c.x;
+                    ci = c.y;
+                } else if (p + 1 < P) {
+                    const c32 c = coef[b * P + p + 1];
+                    cr = double(p + 1) * c.x;
+                    ci = double(p + 1) * c.y;
+                } else {
+                    cr = double(P);
+                }
+            }
+            cu[0][p1][kk] = cr;
+            cu[1][p1][kk] = ci;
+            cu[2][p1][kk] = cr + ci;
+        }
+        for (int e = threadIdx.x; e < NU_QC * NC; e += 256) {
+            const int kk = e / NC, j = e % NC;
+            d2 c = d2{0.0, 0.0};
+            if (k0 + kk < P2) c = cis_rev64(uint64_t(64 * (k0 + kk)) * sT[j]);    // e^{j 2 pi 64 p2 t}
+            vb[0][kk][j] = c.x;
+            vb[1][kk][j] = c.y - c.x;
+            vb[2][kk][j] = c.x + c.y;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s4 = 0; s4 < NU_QC / 4; ++s4) {
+            const int kq = 4 * s4 + (l >> 4), row = 16 * w + (l & 15);
+            const double ar = cu[0][row][kq], ai = cu[1][row][kq], as = cu[2][row][kq];
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+                const int col = 16 * ct + (l & 15);
+                cmfma(acc[ct], as, ar, ai, vb[0][kq][col], vb[1][kq][col], vb[2][kq][col]);
+            }
+        }
+        __syncthreads();
+    }
+    // outer sum: e^{j 2 pi p1 t_q} W[p1][q] over the lane's four rows, then over the
+    // four row groups of the wave (lanes l, l ^ 16, l ^ 32, l ^ 48) and the four waves
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+        const int col = 16 * ct + (l & 15);
+        const uint64_t T = sT[col];
+        double re = 0.0, im = 0.0;
+        d2 u = cis_rev64(uint64_t(16 * w + (l >> 4)) * T);          // e^{j 2 pi p1 t}, p1 = 16 w + 4 j + l / 16
+        const d2 su = cis_rev64(uint64_t(4) * T);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double wr = acc[ct].t1[j] - acc[ct].t3[j], wi = acc[ct].t1[j] + acc[ct].t2[j];
+            re += u.x * wr - u.y * wi;
+            im += u.x * wi + u.y * wr;
+            if (j < 3) u = cmul64(u, su);
+        }
+        re += __shfl_xor(re, 16);
+        im += __shfl_xor(im, 16);
+        re += __shfl_xor(re, 32);
+        im += __shfl_xor(im, 32);
+        if (l < 16) {
+            red[0][w][col] = re;
+            red[1][w][col] = im;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < NC) {
+        const int q = c0 + threadIdx.x;
+        const double re = red[0][0][threadIdx.x] + red[0][1][threadIdx.x] + red[0][2][threadIdx.x] +
+                          red[0][3][threadIdx.x];
+        const double im = red[1][0][threadIdx.x] + red[1][1][threadIdx.x] + red[1][2][threadIdx.x] +
+                          red[1][3][threadIdx.x];
+        if (q < Q) out[b * Q + q] = c32{float(re), float(im)};
+    }
 }
 
 // ------------------------------------------------------------------ pointwise steps
@@ -507,15 +683,22 @@ static int nu_check_launch(const char *what)
 static int nudft1_launch(const double *t, const c32 *amp, c32 *out, int64_t nblocks, int Q, int R, hipStream_t s)
 {
     if (R % 64 == 0) {
-        // matrix-core form; three column tiles per workgroup when the grid still fills the chip
+        // matrix-core form: three column tiles per workgroup when the grid still fills the
+        // chip, else one tile and the instants split over two or four wave groups
         const int R2 = R / 64;
-        const int64_t g3 = (R2 + 47) / 48;
+        const int64_t g3 = (R2 + 47) / 48, g1 = (R2 + 15) / 16;
         if (R2 >= 48 && g3 * nblocks >= 512) {
-            hipLaunchKernelGGL((nudft1_mfma_kernel<3>), dim3(unsigned(g3), unsigned(nblocks)), dim3(256), 0, s, t, amp,
-                               out, Q, R);
+            hipLaunchKernelGGL((nudft1_mfma_kernel<3, 1>), dim3(unsigned(g3), unsigned(nblocks)), dim3(256), 0, s, t,
+                               amp, out, Q, R);
+        } else if (g1 * nblocks >= 1024 || Q <= 2 * NU_QC) {
+            hipLaunchKernelGGL((nudft1_mfma_kernel<1, 1>), dim3(unsigned(g1), unsigned(nblocks)), dim3(256), 0, s, t,
+                               amp, out, Q, R);
+        } else if (g1 * nblocks >= 512 || Q <= 4 * NU_QC) {
+            hipLaunchKernelGGL((nudft1_mfma_kernel<1, 2>), dim3(unsigned(g1), unsigned(nblocks)), dim3(512), 0, s, t,
+                               amp, out, Q, R);
         } else {
-            hipLaunchKernelGGL((nudft1_mfma_kernel<1>), dim3(unsigned((R2 + 15) / 16), unsigned(nblocks)), dim3(256), 0,
-                               s, t, amp, out, Q, R);
+            hipLaunchKernelGGL((nudft1_mfma_kernel<1, 4>), dim3(unsigned(g1), unsigned(nblocks)), dim3(1024), 0, s, t,
+                               amp, out, Q, R);
         }
         return nu_check_launch("nudft_type1 launch");
     }
@@ -535,6 +718,11 @@ static int nudft1_launch(const double *t, const c32 *amp, c32 *out, int64_t nblo
 static int nudft2_launch(const double *t, const c32 *coef, c32 *out, int64_t nblocks, int P, int Q, int deriv,
                          hipStream_t s)
 {
+    if (P % 64 == 0) {
+        hipLaunchKernelGGL((nudft2_mfma_kernel<2>), dim3(unsigned((Q + 31) / 32), unsigned(nblocks)), dim3(256), 0, s,
+                           t, coef, out, P, Q, deriv);
+        return nu_check_launch("nudft_type2 launch");
+    }
     const unsigned gx = unsigned((Q + NU2_TPB - 1) / NU2_TPB);
     hipLaunchKernelGGL((nudft2_kernel<NU2_TPB>), dim3(gx, unsigned(nblocks)), dim3(NU2_TPB), 0, s, t, coef, out, P,
                        Q, deriv);

@@ -42,7 +42,7 @@ def dev(torch, x):
 
 
 @pytest.mark.parametrize("Q,R,unit", [(64, 384, False), (100, 1000, False), (1, 7, False), (256, 4096, True),
-                                      (1024, 1024, False)])
+                                      (1024, 1024, False), (20, 640, False), (300, 1024, True)])
 def test_type1_sum_matches_oracle(env, Q, R, unit):
     torch, NU, _ = env
     B = 3
@@ -69,7 +69,7 @@ def test_type1_sum_wide_matrix_core_tiles(env):
         assert L.rel_err(out[b], L.type1(t[b], amp[b], R)) < 5e-7
 
 
-@pytest.mark.parametrize("P,Q", [(64, 64), (64, 77), (1024, 300), (5, 1)])
+@pytest.mark.parametrize("P,Q", [(64, 64), (64, 77), (1024, 300), (5, 1), (192, 50), (100, 130)])
 def test_type2_sum_matches_oracle(env, P, Q):
     torch, NU, _ = env
     B = 2
@@ -77,7 +77,7 @@ def test_type2_sum_matches_oracle(env, P, Q):
     c = cn(np.random.default_rng(P), (B, P))
     out = NU.nudft_type2(dev(torch, t), dev(torch, c)).cpu().numpy()
     for b in range(B):
-        assert L.rel_err(out[b], L.type2(c[b], t[b])) < 2e-6
+        assert L.rel_err(out[b], L.type2(c[b], t[b])) < (5e-7 if P % 64 == 0 else 2e-6)
 
 
 def test_sums_read_instants_modulo_one(env):
