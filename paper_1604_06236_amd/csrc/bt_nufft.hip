@@ -175,88 +175,97 @@ constexpr int NU_QC = 16;    // contraction depth staged per step of the matrix-
 // (problem, 16 CT columns of r2) with G groups of four waves; group g takes every
 // G-th chunk of 16 instants (more waves per CU when a problem has few columns), and
 // the groups' partial sums are added through LDS at the end.  Wave w of a group owns
-// the rows r1 in [16 w, 16 w + 16).
-template <int CT, int G>
+// the rows r1 in [16 w, 16 w + 16).  With NBUF = 2 the tables of the next chunk are
+// built while the matrix cores work on the current one (one barrier per chunk).
+template <int CT, int G, int NBUF>
 struct Nu1Smem {
     static constexpr int NC = 16 * CT;
     struct Tab {
-        double u[3][64][NU_QC + 1];     // a e^{-j 2 pi r1 t}: re, im, re + im
-        double v[3][NU_QC][NC + 1];     // e^{-j 2 pi 64 r2 t}: re, im - re, re + im
-        uint64_t T[NU_QC];
-        c32 a[NU_QC];
+        double u[2][64][NU_QC + 1];     // a e^{-j 2 pi r1 t}: re, im
+        double v[2][NU_QC][NC + 1];     // e^{-j 2 pi 64 r2 t}: re, im
     };
     union {
-        Tab tab[G];
+        Tab tab[G][NBUF];
         double red[G > 1 ? G - 1 : 1][4][CT][2][4][64];
     };
 };
 
-template <int CT, int G>
+template <int CT, int G, int NBUF>
 __global__ void __launch_bounds__(256 * G) nudft1_mfma_kernel(const double *t, const c32 *amp, c32 *out, int Q, int R)
 {
-    constexpr int NC = 16 * CT;
-    __shared__ Nu1Smem<CT, G> sm;
+    using Sm = Nu1Smem<CT, G, NBUF>;
+    using Tab = typename Sm::Tab;
+    __shared__ Sm sm;
     const int64_t b = blockIdx.y;
     const int R2 = R / 64;
-    const int c0 = blockIdx.x * NC;
+    const int c0 = blockIdx.x * Sm::NC;
     const int g = threadIdx.x >> 8, tx = threadIdx.x & 255;
     const int w = tx >> 6, l = tx & 63;
-    auto &tb = sm.tab[g];
     cacc acc[CT];
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) acc[ct].t1 = acc[ct].t2 = acc[ct].t3 = dd4{0.0, 0.0, 0.0, 0.0};
 
-    const int nit = (Q + G * NU_QC - 1) / (G * NU_QC);      // the same trip count for every group
-    for (int it = 0; it < nit; ++it) {
-        const int q0 = (it * G + g) * NU_QC;
-        if (tx < NU_QC) {
-            const int q = q0 + tx;
-            tb.T[tx] = q < Q ? fixed_instant(t[b * Q + q]) : 0;
-            tb.a[tx] = q < Q ? (amp ? amp[b * Q + q] : c32{1.f, 0.f}) : c32{0.f, 0.f};
-        }
-        __syncthreads();
-        {
-            // thread (qq, i0): rows r1 = i0 + 16 i and columns j = i0 + 16 i, each run from
-            // one exponential and its step e^{-j 2 pi 16 r t}
-            const int qq = tx & 15, i0 = tx >> 4;
-            const uint64_t T = tb.T[qq];
-            const double ax = tb.a[qq].x, ay = tb.a[qq].y;
-            d2 c = cis_rev64(uint64_t(0) - uint64_t(i0) * T);                    // e^{-j 2 pi r1 t}
-            c = d2{ax * c.x - ay * c.y, ax * c.y + ay * c.x};
-            const d2 st = cis_rev64(uint64_t(0) - uint64_t(16) * T);
+    // tables of chunk `it` of this group: thread (qq, i0) fills the rows r1 = i0 + 16 i
+    // and the columns j = i0 + 16 i of instant qq, each run from one exponential and
+    // its step e^{-j 2 pi 16 r t}
+    auto build = [&](int it, Tab &tb) {
+        const int qq = tx & 15, i0 = tx >> 4;
+        const int q = (it * G + g) * NU_QC + qq;
+        const bool live = q < Q;
+        const uint64_t T = live ? fixed_instant(t[b * Q + q]) : 0;
+        const c32 a = live ? (amp ? amp[b * Q + q] : c32{1.f, 0.f}) : c32{0.f, 0.f};
+        const double ax = a.x, ay = a.y;
+        d2 c = cis_rev64(uint64_t(0) - uint64_t(i0) * T);                        // e^{-j 2 pi r1 t}
+        c = d2{ax * c.x - ay * c.y, ax * c.y + ay * c.x};
+        const d2 st = cis_rev64(uint64_t(0) - uint64_t(16) * T);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int r1 = i0 + 16 * i;
-                tb.u[0][r1][qq] = c.x;
-                tb.u[1][r1][qq] = c.y;
-                tb.u[2][r1][qq] = c.x + c.y;
-                c = cmul64(c, st);
-            }
-            const bool live = q0 + qq < Q;
-            d2 v = cis_rev64(uint64_t(0) - uint64_t(64 * (c0 + i0)) * T);         // e^{-j 2 pi 64 r2 t}
-            const d2 sv = CT > 1 ? cis_rev64(uint64_t(0) - uint64_t(64 * 16) * T) : d2{1.0, 0.0};
-#pragma unroll
-            for (int i = 0; i < CT; ++i) {
-                const int j = i0 + 16 * i;
-                const d2 c2 = (live && c0 + j < R2) ? v : d2{0.0, 0.0};
-                tb.v[0][qq][j] = c2.x;
-                tb.v[1][qq][j] = c2.y - c2.x;
-                tb.v[2][qq][j] = c2.x + c2.y;
-                if (i + 1 < CT) v = cmul64(v, sv);
-            }
+        for (int i = 0; i < 4; ++i) {
+            tb.u[0][i0 + 16 * i][qq] = c.x;
+            tb.u[1][i0 + 16 * i][qq] = c.y;
+            if (i < 3) c = cmul64(c, st);
         }
-        __syncthreads();
+        d2 v = cis_rev64(uint64_t(0) - uint64_t(64 * (c0 + i0)) * T);             // e^{-j 2 pi 64 r2 t}
+        const d2 sv = CT > 1 ? cis_rev64(uint64_t(0) - uint64_t(64 * 16) * T) : d2{1.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < CT; ++i) {
+            const int j = i0 + 16 * i;
+            const bool on = live && c0 + j < R2;
+            tb.v[0][qq][j] = on ? v.x : 0.0;
+            tb.v[1][qq][j] = on ? v.y : 0.0;
+            if (i + 1 < CT) v = cmul64(v, sv);
+        }
+    };
+    auto contract = [&](const Tab &tb) {
 #pragma unroll
         for (int s4 = 0; s4 < NU_QC / 4; ++s4) {
             const int kq = 4 * s4 + (l >> 4), row = 16 * w + (l & 15);
-            const double ar = tb.u[0][row][kq], ai = tb.u[1][row][kq], as = tb.u[2][row][kq];
+            const double ar = tb.u[0][row][kq], ai = tb.u[1][row][kq];
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
                 const int col = 16 * ct + (l & 15);
-                cmfma(acc[ct], as, ar, ai, tb.v[0][kq][col], tb.v[1][kq][col], tb.v[2][kq][col]);
+                const double br = tb.v[0][kq][col], bi = tb.v[1][kq][col];
+                cmfma(acc[ct], ar + ai, ar, ai, br, bi - br, br + bi);
             }
         }
+    };
+
+    const int nit = (Q + G * NU_QC - 1) / (G * NU_QC);      // the same trip count for every group
+    if constexpr (NBUF == 1) {
+        for (int it = 0; it < nit; ++it) {
+            build(it, sm.tab[g][0]);
+            __syncthreads();
+            contract(sm.tab[g][0]);
+            __syncthreads();
+        }
+    } else {
+        if (nit > 0) build(0, sm.tab[g][0]);
         __syncthreads();
+        for (int it = 0; it < nit; ++it) {
+            // buffer (it + 1) & 1 was last read in the previous chunk, before its barrier
+            if (it + 1 < nit) build(it + 1, sm.tab[g][(it + 1) & 1]);
+            contract(sm.tab[g][it & 1]);
+            __syncthreads();
+        }
     }
     if constexpr (G > 1) {
         // the tables are dead (last barrier above): reuse their LDS for the group sums
@@ -688,16 +697,16 @@ static int nudft1_launch(const double *t, const c32 *amp, c32 *out, int64_t nblo
         const int R2 = R / 64;
         const int64_t g3 = (R2 + 47) / 48, g1 = (R2 + 15) / 16;
         if (R2 >= 48 && g3 * nblocks >= 512) {
-            hipLaunchKernelGGL((nudft1_mfma_kernel<3, 1>), dim3(unsigned(g3), unsigned(nblocks)), dim3(256), 0, s, t,
+            hipLaunchKernelGGL((nudft1_mfma_kernel<3, 1, 2>), dim3(unsigned(g3), unsigned(nblocks)), dim3(256), 0, s, t,
                                amp, out, Q, R);
         } else if (g1 * nblocks >= 1024 || Q <= 2 * NU_QC) {
-            hipLaunchKernelGGL((nudft1_mfma_kernel<1, 1>), dim3(unsigned(g1), unsigned(nblocks)), dim3(256), 0, s, t,
+            hipLaunchKernelGGL((nudft1_mfma_kernel<1, 1, 2>), dim3(unsigned(g1), unsigned(nblocks)), dim3(256), 0, s, t,
                                amp, out, Q, R);
         } else if (g1 * nblocks >= 512 || Q <= 4 * NU_QC) {
-            hipLaunchKernelGGL((nudft1_mfma_kernel<1, 2>), dim3(unsigned(g1), unsigned(nblocks)), dim3(512), 0, s, t,
+            hipLaunchKernelGGL((nudft1_mfma_kernel<1, 2, 2>), dim3(unsigned(g1), unsigned(nblocks)), dim3(512), 0, s, t,
                                amp, out, Q, R);
         } else {
-            hipLaunchKernelGGL((nudft1_mfma_kernel<1, 4>), dim3(unsigned(g1), unsigned(nblocks)), dim3(1024), 0, s, t,
+            hipLaunchKernelGGL((nudft1_mfma_kernel<1, 4, 1>), dim3(unsigned(g1), unsigned(nblocks)), dim3(1024), 0, s, t,
                                amp, out, Q, R);
         }
         return nu_check_launch("nudft_type1 launch");
