@@ -158,6 +158,59 @@ def test_grid_cap_persistent_loop(T):
     T.select_schedule(K, M, -1, grid_cap=0)
 
 
+@pytest.mark.parametrize("K,M", [(128, 15), (1024, 15), (256, 9)])
+def test_grid_cap_every_direction(T, K, M):
+    """Capped grids (each workgroup loops over several block groups, with the next
+    group's operands prefetched) give every direction's outputs, for every schedule."""
+    B = 13
+    S, taps = _inputs(B, K, M, seed=K + M)
+    y = W.cn01(np.random.default_rng(K), (B, K * M)).astype(np.complex64)
+    y_ref = O.forward(S, taps)
+    sb_ref, tb_ref = O.adjoint(y, taps, S)
+    inv_ref = O.inverse(y, taps)
+    g_ref, tb2_ref = O.inverse_adjoint(y, taps, S)
+    try:
+        for idx in range(len(T.schedules(K, M))):
+            for cap in (1, 3):
+                print(f"case grid_cap K={K} M={M} idx={idx} cap={cap}", flush=True)
+                T.select_schedule(K, M, idx, grid_cap=cap)
+                what = (K, M, idx, cap)
+                assert rel_l2(_host(T.transform_forward(_dev(S), _dev(taps), K, M)), y_ref) < TOL, what
+                sb, tb = T.transform_adjoint(_dev(y), _dev(taps), K, M, coeffs=_dev(S), want_taps_bar=True)
+                assert rel_l2(_host(sb), sb_ref) < TOL and rel_l2(_host(tb), tb_ref) < TOL, what
+                sb2, _ = T.transform_adjoint(_dev(y), _dev(taps), K, M)
+                assert rel_l2(_host(sb2), sb_ref) < TOL, what
+                assert rel_l2(_host(T.transform_inverse(_dev(y), _dev(taps), K, M)), inv_ref) < TOL, what
+                g, tb2 = T.transform_inverse_adjoint(_dev(y), _dev(taps), K, M, coeffs=_dev(S),
+                                                     want_taps_bar=True)
+                assert rel_l2(_host(g), g_ref) < TOL and rel_l2(_host(tb2), tb2_ref) < TOL, what
+    finally:
+        T.select_schedule(K, M, -1, grid_cap=0)
+
+
+def test_benchmark_batch_every_block_group(T):
+    """The benchmark's launch: 4096 blocks of (128, 15) under each schedule at the
+    grid cap of 1024 workgroups (two block groups per workgroup), checked on sampled
+    blocks in both directions."""
+    K, M, B = 128, 15, 4096
+    S, taps = _inputs(B, K, M, seed=99)
+    y = W.cn01(np.random.default_rng(98), (B, K * M)).astype(np.complex64)
+    idx_s = np.sort(np.random.default_rng(0).choice(B, 24, replace=False))
+    idx_s = np.concatenate([idx_s, [0, 1, 2047, 2048, B - 1]])
+    y_ref = O.forward(S[idx_s], taps)
+    sb_ref, _ = O.adjoint(y[idx_s], taps)
+    try:
+        for idx in range(len(T.schedules(K, M))):
+            print(f"case bench batch idx={idx}", flush=True)
+            T.select_schedule(K, M, idx, grid_cap=1024)
+            out = _host(T.transform_forward(_dev(S), _dev(taps), K, M))[idx_s]
+            assert rel_l2(out, y_ref) < TOL, idx
+            sb, _ = T.transform_adjoint(_dev(y), _dev(taps), K, M)
+            assert rel_l2(_host(sb)[idx_s], sb_ref) < TOL, idx
+    finally:
+        T.select_schedule(K, M, -1, grid_cap=0)
+
+
 def test_zero_tap_sets_status(T):
     import torch
     K, M, B = 8, 5, 4
