@@ -43,7 +43,7 @@ def _time_pairs(torch, calls, reps, rounds=3):
     return best
 
 
-def tune_shape(T, K, M, B, caps=(0, 1024, 2048), reps=50, nbuf=4, verbose=True):
+def tune_shape(T, K, M, B, caps=(0, 256, 512, 1024, 2048), reps=50, nbuf=4, verbose=True):
     """Time every compiled schedule of (K, M) at several grid caps on a batch of B
     blocks: forward S -> y and adjoint yb -> sb over `nbuf` rotating buffer sets
     (separate buffers, so neither direction reads what the other just touched)."""

@@ -45,6 +45,13 @@ void register_fused_tuned(std::vector<FusedEntry> &v)
         make_entry<Radices<9, 16, 16>, 128, 1, OPT_SEQ_TWIDDLE | OPT_PAIRED_IO>(256, 9),
         make_entry<Radices<9, 16, 16>, 256, 1, OPT_SEQ_TWIDDLE | OPT_NT>(256, 9),
         make_entry<Radices<5, 4, 4>, 16, 8, OPT_PAIRED_IO>(16, 5),
+        // non-temporal variants of the other plans
+        make_entry<Radices<15, 32, 32>, 512, 1, OPT_NT>(1024, 15),
+        make_entry<Radices<15, 32, 32>, 512, 1, OPT_SEQ_TWIDDLE | OPT_NT>(1024, 15),
+        make_entry<Radices<15, 16, 16, 4>, 1024, 1, OPT_SEQ_TWIDDLE | OPT_NT>(1024, 15),
+        make_entry<Radices<15, 8, 8, 16>, 1024, 1, OPT_NT>(1024, 15),
+        make_entry<Radices<9, 16, 16>, 128, 2, OPT_SEQ_TWIDDLE | OPT_PAIRED_IO | OPT_NT>(256, 9),
+        make_entry<Radices<5, 4, 4>, 16, 8, OPT_PAIRED_IO | OPT_NT>(16, 5),
     };
     v.insert(v.end(), e, e + sizeof(e) / sizeof(e[0]));
 }
