@@ -300,13 +300,13 @@ int nfft_type2(const double *t, const void *coeffs, void *out, int64_t nblocks, 
 
 /* exact type-1 sum, eq. (32): out[b][r] = sum_{q<Q} amp[b][q] e^{-j 2 pi r t[b][q]}, r < R.
    t: float64 [nblocks][Q]; amp: complex64 [nblocks][Q], NULL for unit amplitudes;
-   out: complex64 [nblocks][R].  Q in [1, 1024], R in [1, 65536]. */
+   out: complex64 [nblocks][R].  Q in [1, 65536], R in [1, 65536]. */
 int nudft_type1(const double *t, const void *amp, void *out, int64_t nblocks, int32_t Q, int32_t R,
                 void *stream);
 
 /* exact type-2 sum, eq. (34): out[b][q] = sum_{p<P} coeffs[b][p] e^{+j 2 pi p t[b][q]}, q < Q.
    t: float64 [nblocks][Q]; coeffs: complex64 [nblocks][P]; out: complex64 [nblocks][Q].
-   P in [1, 1024], Q in [1, 65536]. */
+   P in [1, 65536], Q in [1, 65536]. */
 int nudft_type2(const double *t, const void *coeffs, void *out, int64_t nblocks, int32_t P, int32_t Q,
                 void *stream);
 

@@ -10,10 +10,9 @@
 //
 // Numerics.  Instants are turned into 64-bit fixed-point fractions of a cycle,
 // so every phase k t_q mod 1 is formed exactly in integer arithmetic before the
-// sine/cosine of a remainder of at most 1/8 cycle.  Where the frequency count is
-// a multiple of 64 the sums are complex matrix products on the FP64 matrix cores
-// over tables of such exponentials (FP64 sine/cosine); otherwise each term is an
-// FP32 sine/cosine and the terms accumulate in FP64.  The constant phase
+// sine/cosine of a remainder of at most 1/8 cycle.  The exact sums are complex
+// matrix products on the FP64 matrix cores over tables of such exponentials
+// (FP64 sine/cosine); the gridding kernels use an FP32 sine/cosine.  The constant phase
 // P pi + 2 pi sum t of eq. (29) is likewise summed exactly as a fixed-point
 // fraction.  Everything else is FP32.
 #include <hip/hip_runtime.h>
@@ -27,7 +26,7 @@
 
 namespace bt {
 
-constexpr int NU_MAXP = 1024;     // instants / coefficients staged per problem
+constexpr int NU_MAXQ = 65536;    // instants / coefficients / frequencies per problem of the exact sums
 
 // frac(t) as a fixed-point fraction of a cycle: T = frac(t) 2^64
 __device__ __forceinline__ uint64_t fixed_instant(double t)
@@ -70,43 +69,6 @@ __device__ __forceinline__ c32 cis_rev(uint32_t ph)
 // ------------------------------------------------------------------ type-1 sums
 // out[b][r] = sum_{q<Q} amp[b][q] exp(-j 2 pi r t[b][q]),  r < R  (eq. (32));
 // amp == nullptr means unit amplitudes (the delta train z(t) of eq. (14)).
-// Grid: (ceil(R / (TPB RPT)), nblocks); each thread owns RPT outputs.
-template <int TPB, int RPT>
-__global__ void __launch_bounds__(TPB) nudft1_kernel(const double *t, const c32 *amp, c32 *out, int Q, int R)
-{
-    __shared__ uint32_t s_lo[NU_MAXP], s_hi[NU_MAXP];
-    __shared__ c32 s_a[NU_MAXP];
-    const int64_t b = blockIdx.y;
-    for (int q = threadIdx.x; q < Q; q += TPB) {
-        const uint64_t T = fixed_instant(t[b * Q + q]);
-        s_lo[q] = uint32_t(T);
-        s_hi[q] = uint32_t(T >> 32);
-        s_a[q] = amp ? amp[b * Q + q] : c32{1.f, 0.f};
-    }
-    __syncthreads();
-    const int r0 = blockIdx.x * (TPB * RPT) + threadIdx.x;
-    double ax[RPT], ay[RPT];
-#pragma unroll
-    for (int i = 0; i < RPT; ++i) ax[i] = ay[i] = 0.0;
-    for (int q = 0; q < Q; ++q) {
-        const uint32_t lo = s_lo[q], hi = s_hi[q];
-        const c32 A = s_a[q];
-        const double Ax = A.x, Ay = A.y;
-#pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-            const uint32_t r = uint32_t(r0 + i * TPB);
-            const c32 e = cis_rev(0u - phase32(r, lo, hi));         // exp(-j 2 pi r t_q)
-            const double ex = e.x, ey = e.y;
-            ax[i] = fma(Ax, ex, fma(-Ay, ey, ax[i]));
-            ay[i] = fma(Ax, ey, fma(Ay, ex, ay[i]));
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-        const int r = r0 + i * TPB;
-        if (r < R) out[b * R + r] = c32{float(ax[i]), float(ay[i])};
-    }
-}
 
 // exp(+j 2 pi ph / 2^64) in FP64: quadrant split off exactly in integers, the
 // remainder (at most pi/4) through Taylor polynomials of degree 17 / 16, whose
@@ -175,7 +137,8 @@ constexpr int NU_QC = 16;    // contraction depth staged per step of the matrix-
 // (problem, 16 CT columns of r2) with G groups of four waves; group g takes every
 // G-th chunk of 16 instants (more waves per CU when a problem has few columns), and
 // the groups' partial sums are added through LDS at the end.  Wave w of a group owns
-// the rows r1 in [16 w, 16 w + 16).  With NBUF = 2 the tables of the next chunk are
+// the rows r1 in [16 w, 16 w + 16).  R is padded to a multiple of 64; the extra
+// outputs are computed and dropped.  With NBUF = 2 the tables of the next chunk are
 // built while the matrix cores work on the current one (one barrier per chunk).
 template <int CT, int G, int NBUF>
 struct Nu1Smem {
@@ -197,7 +160,7 @@ __global__ void __launch_bounds__(256 * G) nudft1_mfma_kernel(const double *t, c
     using Tab = typename Sm::Tab;
     __shared__ Sm sm;
     const int64_t b = blockIdx.y;
-    const int R2 = R / 64;
+    const int R2 = (R + 63) / 64;       // columns; outputs r >= R of the last one are not stored
     const int c0 = blockIdx.x * Sm::NC;
     const int g = threadIdx.x >> 8, tx = threadIdx.x & 255;
     const int w = tx >> 6, l = tx & 63;
@@ -292,8 +255,8 @@ __global__ void __launch_bounds__(256 * G) nudft1_mfma_kernel(const double *t, c
                 re += sm.red[h][w][ct][0][j][l];
                 im += sm.red[h][w][ct][1][j][l];
             }
-            const int r1 = 16 * w + 4 * j + (l >> 4);
-            if (r2 < R2) out[b * R + r1 + 64 * r2] = c32{float(re), float(im)};
+            const int r = 16 * w + 4 * j + (l >> 4) + 64 * r2;
+            if (r < R) out[b * R + r] = c32{float(re), float(im)};
         }
     }
 }
@@ -302,48 +265,15 @@ __global__ void __launch_bounds__(256 * G) nudft1_mfma_kernel(const double *t, c
 // out[b][q] = sum_{p<P} c_p exp(+j 2 pi p t[b][q]),  q < Q  (eq. (34)).
 // deriv == 0: c_p = coef[b][p].  deriv == 1: the coefficients of L'(z) from the
 // P lower coefficients of the monic L (eq. (16)): c_p = (p+1) coef[b][p+1] for
-// p < P-1, c_{P-1} = P (L_P = 1).  Grid: (ceil(Q / TPB), nblocks).
-template <int TPB>
-__global__ void __launch_bounds__(TPB) nudft2_kernel(const double *t, const c32 *coef, c32 *out, int P, int Q,
-                                                     int deriv)
-{
-    __shared__ c32 s_c[NU_MAXP];
-    const int64_t b = blockIdx.y;
-    for (int p = threadIdx.x; p < P; p += TPB) {
-        c32 c;
-        if (!deriv) {
-            c = coef[b * P + p];
-        } else if (p + 1 < P) {
-            const c32 l = coef[b * P + p + 1];
-            c = c32{float(p + 1) * l.x, float(p + 1) * l.y};
-        } else {
-            c = c32{float(P), 0.f};
-        }
-        s_c[p] = c;
-    }
-    __syncthreads();
-    const int q = blockIdx.x * TPB + threadIdx.x;
-    if (q >= Q) return;
-    const uint64_t T = fixed_instant(t[b * Q + q]);
-    const uint32_t lo = uint32_t(T), hi = uint32_t(T >> 32);
-    double ax = 0.0, ay = 0.0;
-    for (int p = 0; p < P; ++p) {
-        const c32 e = cis_rev(phase32(uint32_t(p), lo, hi));
-        const c32 c = s_c[p];
-        const double ex = e.x, ey = e.y, cx = c.x, cy = c.y;
-        ax = fma(cx, ex, fma(-cy, ey, ax));
-        ay = fma(cx, ey, fma(cy, ex, ay));
-    }
-    out[b * Q + q] = c32{float(ax), float(ay)};
-}
+// p < P-1, c_{P-1} = P (L_P = 1).
 
 // Type-2 sum on the matrix cores.  With p = p1 + 64 p2,
 // s(t_q) = sum_{p1<64} e^{j 2 pi p1 t_q} W[p1][q],  W[p1][q] = sum_{p2} C[p1][p2] V[p2][q],
 // C[p1][p2] = c_{p1 + 64 p2},  V[p2][q] = e^{j 2 pi 64 p2 t_q}:  W is a complex matrix
-// product over P/64 terms (16 per staged step, zero-padded), the outer sum a
+// product over ceil(P/64) terms (16 per staged step, zero-padded), the outer sum a
 // pointwise product with a 64-row reduction.  One workgroup of four waves per
 // (problem, 16 CT instants); wave w owns the rows p1 in [16 w, 16 w + 16).
-// Coefficients as in the direct kernel (deriv: those of L', eq. (16)).
+// Coefficients c_p as described above (deriv: those of L', eq. (16)).
 template <int CT>
 __global__ void __launch_bounds__(256) nudft2_mfma_kernel(const double *t, const c32 *coef, c32 *out, int P, int Q,
                                                          int deriv)
@@ -354,7 +284,7 @@ __global__ void __launch_bounds__(256) nudft2_mfma_kernel(const double *t, const
     __shared__ uint64_t sT[NC];
     __shared__ double red[2][4][NC];
     const int64_t b = blockIdx.y;
-    const int P2 = P / 64;
+    const int P2 = (P + 63) / 64;      // coefficients p >= P of the last column are zero
     const int c0 = blockIdx.x * NC;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     if (threadIdx.x < NC) {
@@ -370,7 +300,7 @@ __global__ void __launch_bounds__(256) nudft2_mfma_kernel(const double *t, const
             const int kk = e / 64, p1 = e % 64;          // consecutive threads: consecutive coefficients
             const int p = p1 + 64 * (k0 + kk);
             double cr = 0.0, ci = 0.0;
-            if (k0 + kk < P2) {
+            if (p < P) {
                 if (!deriv) {
                     const c32 c = coef[b * P + p];
                     cr = c.x;
@@ -675,7 +605,7 @@ __global__ void grid_interp_kernel(const double *t, const c32 *h, c32 *out, int 
 }
 
 // ------------------------------------------------------------------ host side
-constexpr int NU1_TPB = 256, NU1_RPT = 4, NU2_TPB = 256, NU_PW_TPB = 256;
+constexpr int NU_PW_TPB = 256;
 
 static bool nu_aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
@@ -691,35 +621,22 @@ static int nu_check_launch(const char *what)
 
 static int nudft1_launch(const double *t, const c32 *amp, c32 *out, int64_t nblocks, int Q, int R, hipStream_t s)
 {
-    if (R % 64 == 0) {
-        // matrix-core form: three column tiles per workgroup when the grid still fills the
-        // chip, else one tile and the instants split over two or four wave groups
-        const int R2 = R / 64;
-        const int64_t g3 = (R2 + 47) / 48, g1 = (R2 + 15) / 16;
-        if (R2 >= 48 && g3 * nblocks >= 512) {
-            hipLaunchKernelGGL((nudft1_mfma_kernel<3, 1, 2>), dim3(unsigned(g3), unsigned(nblocks)), dim3(256), 0, s, t,
-                               amp, out, Q, R);
-        } else if (g1 * nblocks >= 1024 || Q <= 2 * NU_QC) {
-            hipLaunchKernelGGL((nudft1_mfma_kernel<1, 1, 2>), dim3(unsigned(g1), unsigned(nblocks)), dim3(256), 0, s, t,
-                               amp, out, Q, R);
-        } else if (g1 * nblocks >= 512 || Q <= 4 * NU_QC) {
-            hipLaunchKernelGGL((nudft1_mfma_kernel<1, 2, 2>), dim3(unsigned(g1), unsigned(nblocks)), dim3(512), 0, s, t,
-                               amp, out, Q, R);
-        } else {
-            hipLaunchKernelGGL((nudft1_mfma_kernel<1, 4, 1>), dim3(unsigned(g1), unsigned(nblocks)), dim3(1024), 0, s, t,
-                               amp, out, Q, R);
-        }
-        return nu_check_launch("nudft_type1 launch");
-    }
-    const unsigned gx = unsigned((R + NU1_TPB * NU1_RPT - 1) / (NU1_TPB * NU1_RPT));
-    if (int64_t(gx) * nblocks >= 1024) {
-        hipLaunchKernelGGL((nudft1_kernel<NU1_TPB, NU1_RPT>), dim3(gx, unsigned(nblocks)), dim3(NU1_TPB), 0, s, t,
+    // three column tiles per workgroup when the grid still fills the chip, else one
+    // tile and the instants split over two or four wave groups
+    const int R2 = (R + 63) / 64;
+    const int64_t g3 = (R2 + 47) / 48, g1 = (R2 + 15) / 16;
+    if (R2 >= 48 && g3 * nblocks >= 512) {
+        hipLaunchKernelGGL((nudft1_mfma_kernel<3, 1, 2>), dim3(unsigned(g3), unsigned(nblocks)), dim3(256), 0, s, t,
+                           amp, out, Q, R);
+    } else if (g1 * nblocks >= 1024 || Q <= 2 * NU_QC) {
+        hipLaunchKernelGGL((nudft1_mfma_kernel<1, 1, 2>), dim3(unsigned(g1), unsigned(nblocks)), dim3(256), 0, s, t,
+                           amp, out, Q, R);
+    } else if (g1 * nblocks >= 512 || Q <= 4 * NU_QC) {
+        hipLaunchKernelGGL((nudft1_mfma_kernel<1, 2, 2>), dim3(unsigned(g1), unsigned(nblocks)), dim3(512), 0, s, t,
                            amp, out, Q, R);
     } else {
-        // few outputs per problem: one output per thread, so that the grid fills the chip
-        const unsigned g1 = unsigned((R + NU1_TPB - 1) / NU1_TPB);
-        hipLaunchKernelGGL((nudft1_kernel<NU1_TPB, 1>), dim3(g1, unsigned(nblocks)), dim3(NU1_TPB), 0, s, t, amp,
-                           out, Q, R);
+        hipLaunchKernelGGL((nudft1_mfma_kernel<1, 4, 1>), dim3(unsigned(g1), unsigned(nblocks)), dim3(1024), 0, s, t,
+                           amp, out, Q, R);
     }
     return nu_check_launch("nudft_type1 launch");
 }
@@ -727,14 +644,8 @@ static int nudft1_launch(const double *t, const c32 *amp, c32 *out, int64_t nblo
 static int nudft2_launch(const double *t, const c32 *coef, c32 *out, int64_t nblocks, int P, int Q, int deriv,
                          hipStream_t s)
 {
-    if (P % 64 == 0) {
-        hipLaunchKernelGGL((nudft2_mfma_kernel<2>), dim3(unsigned((Q + 31) / 32), unsigned(nblocks)), dim3(256), 0, s,
-                           t, coef, out, P, Q, deriv);
-        return nu_check_launch("nudft_type2 launch");
-    }
-    const unsigned gx = unsigned((Q + NU2_TPB - 1) / NU2_TPB);
-    hipLaunchKernelGGL((nudft2_kernel<NU2_TPB>), dim3(gx, unsigned(nblocks)), dim3(NU2_TPB), 0, s, t, coef, out, P,
-                       Q, deriv);
+    hipLaunchKernelGGL((nudft2_mfma_kernel<2>), dim3(unsigned((Q + 31) / 32), unsigned(nblocks)), dim3(256), 0, s, t,
+                       coef, out, P, Q, deriv);
     return nu_check_launch("nudft_type2 launch");
 }
 
@@ -1110,7 +1021,7 @@ extern "C" int nfft_type2(const double *t, const void *coeffs, void *out, int64_
 extern "C" int nudft_type1(const double *t, const void *amp, void *out, int64_t nblocks, int32_t Q, int32_t R,
                            void *stream)
 {
-    if (Q < 1 || Q > NU_MAXP || R < 1 || R > 65536) return TF_EUNSUPPORTED;
+    if (Q < 1 || Q > NU_MAXQ || R < 1 || R > NU_MAXQ) return TF_EUNSUPPORTED;
     if (nblocks == 0) return TF_OK;
     if (!nu_blocks_ok(nblocks)) return TF_EUNSUPPORTED;
     if (!t || !out || !nu_aligned(t, 8) || !nu_aligned(out, 8) || (amp && !nu_aligned(amp, 8))) return TF_EINVAL;
@@ -1121,7 +1032,7 @@ extern "C" int nudft_type1(const double *t, const void *amp, void *out, int64_t 
 extern "C" int nudft_type2(const double *t, const void *coeffs, void *out, int64_t nblocks, int32_t P, int32_t Q,
                            void *stream)
 {
-    if (P < 1 || P > NU_MAXP || Q < 1 || Q > 65536) return TF_EUNSUPPORTED;
+    if (P < 1 || P > NU_MAXQ || Q < 1 || Q > NU_MAXQ) return TF_EUNSUPPORTED;
     if (nblocks == 0) return TF_OK;
     if (!nu_blocks_ok(nblocks)) return TF_EUNSUPPORTED;
     if (!t || !coeffs || !out || !nu_aligned(t, 8) || !nu_aligned(coeffs, 8) || !nu_aligned(out, 8))

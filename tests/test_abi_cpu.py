@@ -140,7 +140,7 @@ def test_nufft_host_validation(lib):
     assert lib.nufft_type4_refined(t, x, x, 1, 64, 6, 0.01, ws, big, None) == nat.TF_EINVAL
     assert lib.nufft_type5(t, x, ws, 1, 64, 6, 0.01, ws, big, None) == nat.TF_EINVAL
     # sums
-    assert lib.nudft_type1(t, x, y, 1, 2048, 64, None) == nat.TF_EUNSUPPORTED
+    assert lib.nudft_type1(t, x, y, 1, 65537, 64, None) == nat.TF_EUNSUPPORTED
     assert lib.nudft_type2(t, x, y, 1, 64, 0, None) == nat.TF_EUNSUPPORTED
     assert lib.nfft_workspace_size(1, 1000) == 0 and lib.nfft_workspace_size(1, 6144) > 0
     assert lib.nfft_type1(t, x, y, 1, 64, 1000, ws, big, None) == nat.TF_EUNSUPPORTED
