@@ -149,7 +149,7 @@ struct Nu1Smem {
     };
     union {
         Tab tab[G][NBUF];
-        double red[G > 1 ? G - 1 : 1][4][CT][2][4][64];
+        double red[G > 1 ? G - 1 : 1][4][G > 1 ? CT : 1][2][4][64];    // group sums (G > 1 only)
     };
 };
 
