@@ -115,9 +115,6 @@ struct SplitArgs {
 };
 
 constexpr int ST = 512;   // threads per workgroup (8 waves)
-#ifndef SPLIT_PREFETCH
-#define SPLIT_PREFETCH 0      // holding the next block in registers spills the 32-point stages
-#endif
 
 // k slot -> row index of the 32-wide chunk (see the header comment)
 __device__ __forceinline__ int kperm32(int g, int j) { return j < 4 ? 4 * g + j : 16 + 4 * g + j - 4; }
@@ -168,38 +165,36 @@ __global__ void __launch_bounds__(ST) split_kernel(SplitArgs a)
             fk[t].set(j, a.fk[kr * KS + 16 * t + c]);
         }
 
-    // stage-A operands of one block in registers: each wave owns TPW column tiles;
-    // the next block's are fetched while the current one runs its B stages
+    // stage-A operands of one block in registers (each wave owns TPW column tiles),
+    // with the input-side taps.  The next block's are fetched after the B stages, so
+    // that they are in flight during the write-out (held across the B stages they
+    // would spill the 32-point stages)
     constexpr int TPW = NT / (ST / 64);
     static_assert(NT % (ST / 64) == 0, "stage-A tiles must divide among the waves");
     c32 xin[TPW][4];
+    float tin[SIDE == SIDE_IN ? TPW : 1][SIDE == SIDE_IN ? 4 : 1];
+    // every call overwrites all of xin / tin (zeros past the batch), so that they
+    // are dead between stage A and the next fetch
     auto fetch = [&](int64_t bb) {
-        const c32 *inb = a.in + bb * N;
+        const bool valid = bb < a.nblocks;
+        const int64_t bc = valid ? bb : 0;
+        const c32 *inb = a.in + bc * N;
+        const float *tpb = a.taps + bc * a.tap_stride;
 #pragma unroll
         for (int i = 0; i < TPW; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int r = 4 * g + j;
                 const int n = 16 * (w + i * (ST / 64)) + c + K * r;
-                xin[i][j] = r < M ? inb[n] : c32{0.f, 0.f};
+                xin[i][j] = (valid && r < M) ? inb[n] : c32{0.f, 0.f};
+                if constexpr (SIDE == SIDE_IN) tin[i][j] = (valid && r < M) ? tpb[n] : 0.f;
             }
     };
 
+    fetch(blockIdx.x);
     for (int64_t b = blockIdx.x; b < a.nblocks; b += gridDim.x) {
-        if (!SPLIT_PREFETCH || b == blockIdx.x) fetch(b);
         c32 *outb = a.out + b * N;
         const float *tp = a.taps + b * a.tap_stride;
-        // input-side taps of this block, all issued at once (one latency per block)
-        float tin[SIDE == SIDE_IN ? TPW : 1][SIDE == SIDE_IN ? 4 : 1];
-        if constexpr (SIDE == SIDE_IN) {
-#pragma unroll
-            for (int i = 0; i < TPW; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int r = 4 * g + j;
-                    tin[i][j] = r < M ? tp[16 * (w + i * (ST / 64)) + c + K * r] : 0.f;
-                }
-        }
 
         // ---- stage A: per 16-column tile of p, U = F_M Z, then the coset twiddle
         float sZ = 1.0f;
@@ -244,8 +239,6 @@ __global__ void __launch_bounds__(ST) split_kernel(SplitArgs a)
                 if (m < M) umax = fmaxf(umax, fmaxf(fabsf(u.x), fabsf(u.y)));
             }
         }
-        // the next block's stage-A operands, in flight during the B stages
-        if (SPLIT_PREFETCH && b + gridDim.x < a.nblocks) fetch(b + gridDim.x);
         __syncthreads();
         float sU = 1.0f;
         if constexpr (P::scaled) {
@@ -315,14 +308,23 @@ __global__ void __launch_bounds__(ST) split_kernel(SplitArgs a)
             }
         }
         __syncthreads();
+        fetch(b + gridDim.x);
 
-        // ---- natural-order write-out: y_u with u = M q + m
+        // ---- natural-order write-out: y_u with u = M q + m; (q, m) advance by ST
+        //      per step without a division
+        const int dq = ST / M, dm = ST - dq * M;
+        int q = int(threadIdx.x) / M, m = int(threadIdx.x) - q * M;
         for (int u = threadIdx.x; u < N; u += ST) {
-            const int q = u / M, m = u - q * M;
             c32 y = U[m * RS + q];
             if (conj_io) y = conj(y);
             if (SIDE == SIDE_OUT) y = scale(y, tp[u]);
             outb[u] = y;
+            q += dq;
+            m += dm;
+            if (m >= M) {
+                m -= M;
+                ++q;
+            }
         }
         __syncthreads();
     }
