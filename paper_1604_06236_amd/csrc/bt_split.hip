@@ -314,16 +314,28 @@ __global__ void __launch_bounds__(ST) split_kernel(SplitArgs a)
         //      per step without a division
         const int dq = ST / M, dm = ST - dq * M;
         int q = int(threadIdx.x) / M, m = int(threadIdx.x) - q * M;
-        for (int u = threadIdx.x; u < N; u += ST) {
-            c32 y = U[m * RS + q];
-            if (conj_io) y = conj(y);
-            if (SIDE == SIDE_OUT) y = scale(y, tp[u]);
-            outb[u] = y;
-            q += dq;
-            m += dm;
-            if (m >= M) {
-                m -= M;
-                ++q;
+        // eight outputs per thread per step, their output-side taps loaded together
+        for (int u0 = threadIdx.x; u0 < N; u0 += 8 * ST) {
+            float tv[8];
+            if constexpr (SIDE == SIDE_OUT) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) tv[k] = u0 + k * ST < N ? tp[u0 + k * ST] : 0.f;
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int u = u0 + k * ST;
+                if (u < N) {
+                    c32 y = U[m * RS + q];
+                    if (conj_io) y = conj(y);
+                    if constexpr (SIDE == SIDE_OUT) y = scale(y, tv[k]);
+                    outb[u] = y;
+                }
+                q += dq;
+                m += dm;
+                if (m >= M) {
+                    m -= M;
+                    ++q;
+                }
             }
         }
         __syncthreads();

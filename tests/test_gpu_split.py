@@ -77,11 +77,21 @@ def test_split_precision_config_full_size(T):
     y32 = _host(T.transform_forward(dS, dt, K, M))
     idx = np.array([0, 517, 1023, 2047])
     ref = O.forward(S[idx], taps)
+    yb = W.cn01(np.random.default_rng(31), S.shape).astype(np.complex64)
+    dyb = _dev(yb)
+    sb32, _ = T.transform_adjoint(dyb, dt, K, M)
+    sb32 = _host(sb32)
+    sb_ref, _ = O.adjoint(yb[idx], taps)
     for compute in ("split_bf16", "split_fp16"):
         print(f"case split full {compute}", flush=True)
         y = _host(T.transform_forward(dS, dt, K, M, compute=compute))
         assert rel_l2(y[idx], ref) < BOUND[compute]
         assert rel_l2(y, y32.astype(np.complex128)) < BOUND[compute] + 1e-6
+        # the adjoint over the same persistent launch (eight blocks per workgroup)
+        sb, _ = T.transform_adjoint(dyb, dt, K, M, compute=compute)
+        sb = _host(sb)
+        assert rel_l2(sb[idx], sb_ref) < BOUND[compute]
+        assert rel_l2(sb, sb32.astype(np.complex128)) < BOUND[compute] + 1e-6
 
 
 def test_split_rejects_unsupported(T):
