@@ -153,8 +153,8 @@ struct Nu1Smem {
     };
 };
 
-template <int CT, int G, int NBUF>
-__global__ void __launch_bounds__(256 * G) nudft1_mfma_kernel(const double *t, const c32 *amp, c32 *out, int Q, int R)
+template <int CT, int G, int NBUF, int MINW = 1>
+__global__ void __launch_bounds__(256 * G, MINW) nudft1_mfma_kernel(const double *t, const c32 *amp, c32 *out, int Q, int R)
 {
     using Sm = Nu1Smem<CT, G, NBUF>;
     using Tab = typename Sm::Tab;
@@ -275,12 +275,12 @@ __global__ void __launch_bounds__(256 * G) nudft1_mfma_kernel(const double *t, c
 // (problem, 16 CT instants); wave w owns the rows p1 in [16 w, 16 w + 16).
 // Coefficients c_p as described above (deriv: those of L', eq. (16)).
 template <int CT>
-__global__ void __launch_bounds__(256) nudft2_mfma_kernel(const double *t, const c32 *coef, c32 *out, int P, int Q,
+__global__ void __launch_bounds__(256, 4) nudft2_mfma_kernel(const double *t, const c32 *coef, c32 *out, int P, int Q,
                                                          int deriv)
 {
     constexpr int NC = 16 * CT;
-    __shared__ double cu[3][64][NU_QC + 1];     // C: re, im, re + im
-    __shared__ double vb[3][NU_QC][NC + 1];     // V: re, im - re, re + im
+    __shared__ double cu[2][64][NU_QC + 1];     // C: re, im
+    __shared__ double vb[2][NU_QC][NC + 1];     // V: re, im
     __shared__ uint64_t sT[NC];
     __shared__ double red[2][4][NC];
     const int64_t b = blockIdx.y;
@@ -315,25 +315,24 @@ __global__ void __launch_bounds__(256) nudft2_mfma_kernel(const double *t, const
             }
             cu[0][p1][kk] = cr;
             cu[1][p1][kk] = ci;
-            cu[2][p1][kk] = cr + ci;
         }
         for (int e = threadIdx.x; e < NU_QC * NC; e += 256) {
             const int kk = e / NC, j = e % NC;
             d2 c = d2{0.0, 0.0};
             if (k0 + kk < P2) c = cis_rev64(uint64_t(64 * (k0 + kk)) * sT[j]);    // e^{j 2 pi 64 p2 t}
             vb[0][kk][j] = c.x;
-            vb[1][kk][j] = c.y - c.x;
-            vb[2][kk][j] = c.x + c.y;
+            vb[1][kk][j] = c.y;
         }
         __syncthreads();
 #pragma unroll
         for (int s4 = 0; s4 < NU_QC / 4; ++s4) {
             const int kq = 4 * s4 + (l >> 4), row = 16 * w + (l & 15);
-            const double ar = cu[0][row][kq], ai = cu[1][row][kq], as = cu[2][row][kq];
+            const double ar = cu[0][row][kq], ai = cu[1][row][kq];
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
                 const int col = 16 * ct + (l & 15);
-                cmfma(acc[ct], as, ar, ai, vb[0][kq][col], vb[1][kq][col], vb[2][kq][col]);
+                const double br = vb[0][kq][col], bi = vb[1][kq][col];
+                cmfma(acc[ct], ar + ai, ar, ai, br, bi - br, br + bi);
             }
         }
         __syncthreads();
@@ -626,7 +625,7 @@ static int nudft1_launch(const double *t, const c32 *amp, c32 *out, int64_t nblo
     const int R2 = (R + 63) / 64;
     const int64_t g3 = (R2 + 47) / 48, g1 = (R2 + 15) / 16;
     if (R2 >= 48 && g3 * nblocks >= 512) {
-        hipLaunchKernelGGL((nudft1_mfma_kernel<3, 1, 2>), dim3(unsigned(g3), unsigned(nblocks)), dim3(256), 0, s, t,
+        hipLaunchKernelGGL((nudft1_mfma_kernel<3, 2, 1, 4>), dim3(unsigned(g3), unsigned(nblocks)), dim3(512), 0, s, t,
                            amp, out, Q, R);
     } else if (g1 * nblocks >= 1024 || Q <= 2 * NU_QC) {
         hipLaunchKernelGGL((nudft1_mfma_kernel<1, 1, 2>), dim3(unsigned(g1), unsigned(nblocks)), dim3(256), 0, s, t,
