@@ -242,8 +242,9 @@ int transform_ragged_execute(tf_ragged_plan plan, int32_t direction, const void 
  *                 to the truncation ratio mu = e^{-2 pi (eta P - 1) a}/(eta P - 1)
  *   workspace   : device scratch of nufft_workspace_size(nblocks, P, eta)
  *                 bytes, 256-byte aligned, owned by the caller
- * Arithmetic: exact fixed-point phases, FP32 terms, FP64 accumulation of the
- * non-uniform sums, FP32 everywhere else.  All work is asynchronous on
+ * Arithmetic: exact fixed-point phases; the exact non-uniform sums in FP64
+ * (FP64 exponential tables, products on the FP64 matrix cores); FP32 everywhere
+ * else.  All work is asynchronous on
  * `stream`; errors are reported before any launch (TF_EINVAL for bad pointers,
  * overlaps or a, TF_EUNSUPPORTED for P/eta outside the ranges, TF_EWORKSPACE).
  * --------------------------------------------------------------------------- */
@@ -261,6 +262,21 @@ size_t nufft_workspace_size_ex(int64_t nblocks, int32_t P, int32_t eta, int32_t 
 int nufft_solve(int32_t type, int32_t flags, const double *t, const void *in, void *out,
                 int64_t nblocks, int32_t P, int32_t eta, double a, void *workspace,
                 size_t workspace_bytes, void *stream);
+
+/* The same in two steps, for several inputs on the same instants.  nufft_setup
+   computes the part of both methods that depends on the instants only (the
+   filters of eq. (8) and eq. (41), the kernel samples of eq. (28)-(29), the
+   Lagrange coefficients of eq. (43) and the derivative samples of eq. (16)) into
+   the workspace; nufft_apply then runs type 4 or 5 (with NUFFT_REFINE if asked)
+   from that workspace, as often as wanted, and leaves the setup intact.  The
+   caller guarantees that the workspace holds a setup of the same t, nblocks, P,
+   eta and a; NUFFT_GRIDDING may differ between the two calls if the workspace is
+   large enough for the gridding flag of each.  In nufft_setup the flags select
+   only how its sums are evaluated.  Errors as for nufft_solve. */
+int nufft_setup(int32_t flags, const double *t, int64_t nblocks, int32_t P, int32_t eta, double a,
+                void *workspace, size_t workspace_bytes, void *stream);
+int nufft_apply(int32_t type, int32_t flags, const double *t, const void *in, void *out, int64_t nblocks,
+                int32_t P, int32_t eta, double a, void *workspace, size_t workspace_bytes, void *stream);
 
 /* type 5 (inverse of eq. (34), the system eq. (48)): coefficients S_p, p < P,
    from samples s(t_q).  samples in: complex64 [nblocks][P]; coeffs out: same. */

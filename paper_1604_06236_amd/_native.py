@@ -36,7 +36,8 @@ EXPORTED = (
     "transform_ragged_plan_create", "transform_ragged_plan_create_ex", "transform_ragged_plan_destroy",
     "transform_ragged_execute", "transform_decimated", "transform_decimated_adjoint",
     "nufft_workspace_size", "nufft_type5", "nufft_type4", "nufft_type5_refined", "nufft_type4_refined",
-    "nudft_type1", "nudft_type2", "nufft_workspace_size_ex", "nufft_solve", "nfft_workspace_size",
+    "nudft_type1", "nudft_type2", "nufft_workspace_size_ex", "nufft_solve", "nufft_setup", "nufft_apply",
+    "nfft_workspace_size",
     "nfft_type1", "nfft_type2",
 )
 
@@ -95,6 +96,8 @@ def load() -> ctypes.CDLL:
     lib.nufft_workspace_size_ex.argtypes = [i64, i32, i32, i32]
     lib.nufft_workspace_size_ex.restype = sz
     lib.nufft_solve.argtypes = [i32, i32, vp, vp, vp, i64, i32, i32, ctypes.c_double, vp, sz, vp]
+    lib.nufft_setup.argtypes = [i32, vp, i64, i32, i32, ctypes.c_double, vp, sz, vp]
+    lib.nufft_apply.argtypes = [i32, i32, vp, vp, vp, i64, i32, i32, ctypes.c_double, vp, sz, vp]
     lib.nfft_workspace_size.argtypes = [i64, i32]
     lib.nfft_workspace_size.restype = sz
     lib.nfft_type1.argtypes = [vp, vp, vp, i64, i32, i32, vp, sz, vp]

@@ -857,16 +857,21 @@ static bool nu_grid_ok(int P, int eta)
     return grid_shape(P * eta, &n, &K, &M) && grid_shape(P, &n, &K, &M);
 }
 
+// phases of a call: the setup (instants only), the application to one input, or both
+enum { NU_SETUP = 1, NU_APPLY = 2 };
+
 static int nufft_run(int kind, int flags, const double *t, const void *in, void *out, int64_t nblocks, int P,
-                     int eta, double a, void *ws, size_t ws_bytes, void *stream)
+                     int eta, double a, void *ws, size_t ws_bytes, void *stream, int phases = NU_SETUP | NU_APPLY)
 {
     const bool refine = flags & NUFFT_REFINE, gridding = flags & NUFFT_GRIDDING;
+    const bool apply = phases & NU_APPLY;
     if (flags & ~(NUFFT_REFINE | NUFFT_GRIDDING)) return TF_EINVAL;
     if (!nu_shape_ok(P, eta) || (gridding && !nu_grid_ok(P, eta))) return TF_EUNSUPPORTED;
     if (!(a > 0.0) || !std::isfinite(a)) return TF_EINVAL;
     if (nblocks == 0) return TF_OK;                       // an empty batch is a no-op
     if (!nu_blocks_ok(nblocks)) return TF_EINVAL;
-    if (!t || !in || !out || !nu_aligned(t, 8) || !nu_aligned(in, 8) || !nu_aligned(out, 8)) return TF_EINVAL;
+    if (!t || !nu_aligned(t, 8)) return TF_EINVAL;
+    if (apply && (!in || !out || !nu_aligned(in, 8) || !nu_aligned(out, 8))) return TF_EINVAL;
     const NuLayout l = nu_layout(nblocks, P, eta, gridding);
     if (!ws || ws_bytes < l.total || !nu_aligned(ws, 256)) return TF_EWORKSPACE;
     const size_t io_bytes = size_t(nblocks) * P * sizeof(c32);
@@ -874,11 +879,11 @@ static int nufft_run(int kind, int flags, const double *t, const void *in, void 
                     pi = reinterpret_cast<uintptr_t>(in), pt = reinterpret_cast<uintptr_t>(t);
     const size_t t_bytes = size_t(nblocks) * P * sizeof(double);
     auto ov = [](uintptr_t x, size_t xb, uintptr_t y, size_t yb) { return x < y + yb && y < x + xb; };
-    if (ov(po, io_bytes, pw, l.total) || ov(pi, io_bytes, pw, l.total) || ov(pt, t_bytes, pw, l.total) ||
-        ov(po, io_bytes, pt, t_bytes))
+    if (ov(pt, t_bytes, pw, l.total)) return TF_EINVAL;
+    if (apply && (ov(po, io_bytes, pw, l.total) || ov(pi, io_bytes, pw, l.total) || ov(po, io_bytes, pt, t_bytes)))
         return TF_EINVAL;
     // the refinement reads the input again after the first pass has written the output
-    if (refine && ov(po, io_bytes, pi, io_bytes)) return TF_EINVAL;
+    if (apply && refine && ov(po, io_bytes, pi, io_bytes)) return TF_EINVAL;
 
     char *w = static_cast<char *>(ws);
     NuBufs b;
@@ -900,7 +905,8 @@ static int nufft_run(int kind, int flags, const double *t, const void *in, void 
     const c32 *x = reinterpret_cast<const c32 *>(in);
     c32 *y = reinterpret_cast<c32 *>(out);
     int rc;
-    if ((rc = nu_setup(t, nblocks, P, eta, a, b, stream))) return rc;
+    if ((phases & NU_SETUP) && (rc = nu_setup(t, nblocks, P, eta, a, b, stream))) return rc;
+    if (!apply) return TF_OK;
     if ((rc = nu_apply(kind, t, x, y, nblocks, P, a, b, stream))) return rc;
     if (!refine) return TF_OK;
 
@@ -940,6 +946,19 @@ extern "C" int nufft_solve(int32_t type, int32_t flags, const double *t, const v
 {
     if (type != 4 && type != 5) return TF_EINVAL;
     return nufft_run(type, flags, t, in, out, nblocks, P, eta, a, workspace, workspace_bytes, stream);
+}
+
+extern "C" int nufft_setup(int32_t flags, const double *t, int64_t nblocks, int32_t P, int32_t eta, double a,
+                           void *workspace, size_t workspace_bytes, void *stream)
+{
+    return nufft_run(5, flags, t, nullptr, nullptr, nblocks, P, eta, a, workspace, workspace_bytes, stream, NU_SETUP);
+}
+
+extern "C" int nufft_apply(int32_t type, int32_t flags, const double *t, const void *in, void *out, int64_t nblocks,
+                           int32_t P, int32_t eta, double a, void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (type != 4 && type != 5) return TF_EINVAL;
+    return nufft_run(type, flags, t, in, out, nblocks, P, eta, a, workspace, workspace_bytes, stream, NU_APPLY);
 }
 
 extern "C" int nufft_type5(const double *t, const void *samples, void *coeffs, int64_t nblocks, int32_t P,

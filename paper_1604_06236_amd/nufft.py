@@ -71,6 +71,44 @@ def nufft_solve(kind: int, t: torch.Tensor, x: torch.Tensor, eta: int, a: float,
     return out
 
 
+def nufft_setup(t: torch.Tensor, eta: int, a: float, *, gridding: bool = False,
+                workspace: Optional[torch.Tensor] = None, refine: bool = False) -> torch.Tensor:
+    """The part of both methods that depends on the instants only (filters, kernel
+    samples eq. (28)-(29), Lagrange coefficients eq. (43), derivative samples
+    eq. (16)), into a workspace that nufft_apply reuses; returns the workspace.
+    `refine` only sizes the workspace for refined applications."""
+    _check(t, "t", torch.float64)
+    B, P = t.shape
+    flags = (NUFFT_REFINE if refine else 0) | (NUFFT_GRIDDING if gridding else 0)
+    need = nufft_workspace_size(B, P, eta, flags)
+    if need == 0:
+        nat.check("nufft_setup", nat.TF_EUNSUPPORTED)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=t.device)
+    if workspace.numel() < need:
+        raise ValueError(f"workspace needs {need} bytes")
+    nat.check("nufft_setup", nat.load().nufft_setup(
+        NUFFT_GRIDDING if gridding else 0, _ptr(t), B, P, eta, float(a), _ptr(workspace), workspace.numel(),
+        _stream(t.device)))
+    return workspace
+
+
+def nufft_apply(kind: int, t: torch.Tensor, x: torch.Tensor, eta: int, a: float, workspace: torch.Tensor, *,
+                refine: bool = False, gridding: bool = False,
+                out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """nufft_solve from a workspace prepared by nufft_setup for the same t, eta, a."""
+    _check(t, "t", torch.float64)
+    B, P = t.shape
+    _check(x, "input", torch.complex64, (B, P))
+    out = torch.empty_like(x) if out is None else out
+    _check(out, "out", torch.complex64, (B, P))
+    flags = (NUFFT_REFINE if refine else 0) | (NUFFT_GRIDDING if gridding else 0)
+    nat.check("nufft_apply", nat.load().nufft_apply(
+        int(kind), flags, _ptr(t), _ptr(x), _ptr(out), B, P, eta, float(a), _ptr(workspace),
+        workspace.numel(), _stream(x.device)))
+    return out
+
+
 def nufft_type5(t: torch.Tensor, samples: torch.Tensor, eta: int, a: float, *,
                 out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
                 refine: bool = False, gridding: bool = False):

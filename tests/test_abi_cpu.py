@@ -139,6 +139,16 @@ def test_nufft_host_validation(lib):
     assert lib.nufft_type5(None, x, y, 1, 64, 6, 0.01, ws, big, None) == nat.TF_EINVAL
     assert lib.nufft_type4_refined(t, x, x, 1, 64, 6, 0.01, ws, big, None) == nat.TF_EINVAL
     assert lib.nufft_type5(t, x, ws, 1, 64, 6, 0.01, ws, big, None) == nat.TF_EINVAL
+    # setup once, apply many: the setup needs no input or output, the application does
+    assert lib.nufft_setup(0, None, 0, 64, 6, 0.01, None, 0, None) == nat.TF_OK
+    assert lib.nufft_setup(0, None, 1, 64, 6, 0.01, ws, big, None) == nat.TF_EINVAL
+    assert lib.nufft_setup(0, t, 1, 64, 6, 0.01, ws, need - 1, None) == nat.TF_EWORKSPACE
+    assert lib.nufft_setup(8, t, 1, 64, 6, 0.01, ws, big, None) == nat.TF_EINVAL
+    assert lib.nufft_setup(0, vp(1 << 33), 1, 64, 6, 0.01, ws, big, None) == nat.TF_EINVAL   # t inside ws
+    assert lib.nufft_apply(3, 0, t, x, y, 1, 64, 6, 0.01, ws, big, None) == nat.TF_EINVAL
+    assert lib.nufft_apply(5, 0, t, None, y, 1, 64, 6, 0.01, ws, big, None) == nat.TF_EINVAL
+    assert lib.nufft_apply(4, 1, t, x, x, 1, 64, 6, 0.01, ws, big, None) == nat.TF_EINVAL
+    assert lib.nufft_apply(5, 0, t, x, y, 1, 2048, 6, 0.01, ws, big, None) == nat.TF_EUNSUPPORTED
     # sums
     assert lib.nudft_type1(t, x, y, 1, 65537, 64, None) == nat.TF_EUNSUPPORTED
     assert lib.nudft_type2(t, x, y, 1, 64, 0, None) == nat.TF_EUNSUPPORTED

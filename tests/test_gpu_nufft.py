@@ -263,6 +263,31 @@ def test_gridding_shape_limits(env):
     assert nat.load().nfft_workspace_size(1, 6144) > 0
 
 
+@pytest.mark.parametrize("gridding", [False, True])
+def test_setup_once_apply_many(env, gridding):
+    """nufft_setup + nufft_apply (type 5, type 4, type 5 again, refined) reproduce
+    the one-call solves bit for bit, and the applications leave the setup intact."""
+    torch, NU, _ = env
+    B, P, eta = 5, 256, 4
+    a = NU.damping_for(1e-7, eta, P)
+    t = dev(torch, inst(B, P, 41))
+    rng = np.random.default_rng(42)
+    s = dev(torch, cn(rng, (B, P)))
+    A = dev(torch, cn(rng, (B, P)))
+    print(f"case setup/apply gridding={gridding}", flush=True)
+    ws = NU.nufft_setup(t, eta, a, gridding=gridding, refine=True)
+    S5 = NU.nufft_apply(5, t, s, eta, a, ws, gridding=gridding).cpu().numpy()
+    a4 = NU.nufft_apply(4, t, A, eta, a, ws, gridding=gridding).cpu().numpy()
+    S5b = NU.nufft_apply(5, t, s, eta, a, ws, gridding=gridding).cpu().numpy()
+    S5r = NU.nufft_apply(5, t, s, eta, a, ws, gridding=gridding, refine=True).cpu().numpy()
+    a4r = NU.nufft_apply(4, t, A, eta, a, ws, gridding=gridding, refine=True).cpu().numpy()
+    assert np.array_equal(S5, NU.nufft_type5(t, s, eta, a, gridding=gridding).cpu().numpy())
+    assert np.array_equal(a4, NU.nufft_type4(t, A, eta, a, gridding=gridding).cpu().numpy())
+    assert np.array_equal(S5b, S5)
+    assert np.array_equal(S5r, NU.nufft_type5(t, s, eta, a, gridding=gridding, refine=True).cpu().numpy())
+    assert np.array_equal(a4r, NU.nufft_type4(t, A, eta, a, gridding=gridding, refine=True).cpu().numpy())
+
+
 def test_empty_batch_is_a_no_op(env):
     torch, NU, nat = env
     lib = nat.load()
