@@ -203,14 +203,7 @@ def compare(T, sets, taps, K, M, B, blocks_per_s, args):
     steps = max(10, args.steps // 10)
 
     def timeit(fn):
-        for i in range(3):
-            fn(i)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(steps):
-            fn(i)
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / steps
+        return _timeit(fn, steps)
 
     def plain(i):
         S, y, yb, sb = sets[i % len(sets)]
@@ -233,11 +226,20 @@ def compare(T, sets, taps, K, M, B, blocks_per_s, args):
     return res
 
 
-def _timeit(fn, steps, warmup=3):
+def _timeit(fn, steps, warmup=3, warm_s=0.2):
+    """Seconds per call of fn over `steps` calls, after `warmup` calls and an untimed
+    pre-warm of about warm_s seconds (the GPU may have idled during host work, such as
+    an oracle reference, and its clocks need to settle)."""
     import torch
     for i in range(warmup):
         fn(i)
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    i = 0
+    while time.perf_counter() - t0 < warm_s and i < 10000:
+        fn(i)
+        i += 1
+        torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
         fn(i)
