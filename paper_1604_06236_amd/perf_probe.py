@@ -21,7 +21,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--what", default="forward",
                     choices=["forward", "adjoint", "forward_adjoint", "ragged", "split_bf16",
-                             "split_fp16", "differentiation", "decimated", "nufft", "all"])
+                             "split_fp16", "differentiation", "decimated", "nufft", "schedules", "all"])
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--copy-mib", type=int, default=256)
     ap.add_argument("--config", default=None,
@@ -93,6 +93,27 @@ def run(what, reps, T, W, np, torch, config=None):
         plan.close()
         print(f"ragged: {reps} x (forward, adjoint, adjoint with tap gradient) over {lay.K.size} blocks",
               flush=True)
+        return
+    if what == "schedules":
+        # Every fused schedule for the workload's (K, M), in table order, at grid cap 1024:
+        # the dispatch sequence is (forward, adjoint) x reps per schedule.
+        c = W.CONFIGS[config or "precision"]
+        S_h, taps_h = W.make_uniform(c)
+        S = torch.from_numpy(S_h).to(dev)
+        taps = torch.from_numpy(taps_h).to(dev)
+        y = torch.empty_like(S)
+        sb = torch.empty_like(S)
+        idx0, cap0, _ = T.selected_schedule(c.K, c.M)
+        try:
+            for idx, d in enumerate(T.schedules(c.K, c.M)):
+                T.select_schedule(c.K, c.M, idx, grid_cap=1024)
+                for _ in range(reps):
+                    T.transform_forward(S, taps, c.K, c.M, out=y)
+                    T.transform_adjoint(y, taps, c.K, c.M, out=sb)
+                torch.cuda.synchronize()
+                print(idx, d["radices"], d["threads_per_block"], d["nontemporal"], flush=True)
+        finally:
+            T.select_schedule(c.K, c.M, idx0, cap0)
         return
     cfg = {"split_bf16": "precision", "split_fp16": "precision",
            "differentiation": "differentiation"}.get(what, config or "plain_gpu")
