@@ -342,10 +342,14 @@ def extras(T, W, args):
     d = torch.empty((B, K), dtype=torch.complex64, device=dev)
     db = torch.from_numpy(W.cn01(np.random.default_rng(10), (B, K)).astype(np.complex64)).to(dev)
     sb = torch.empty_like(S)
+    # rotating copies of the large operands (about 0.5 GB in all), so that a step does not
+    # find the previous step's data in the 256 MB last-level cache
+    dsets = [(S, sb)] + [(S.clone(), torch.empty_like(S)) for _ in range(3)]
 
     def decstep(i):
-        T.transform_decimated(S, taps, K, M, out=d)
-        T.transform_decimated_adjoint(db, taps, K, M, out=sb)
+        Si, sbi = dsets[i % len(dsets)]
+        T.transform_decimated(Si, taps, K, M, out=d)
+        T.transform_decimated_adjoint(db, taps, K, M, out=sbi)
 
     t = _timeit(decstep, steps)
     byts = (16.0 * N + 16.0 * K) * B
@@ -356,7 +360,7 @@ def extras(T, W, args):
                         "frac_hbm_peak": round(byts / t / 1e9 / HBM_PEAK_GBS, 4),
                         "rel_l2_forward": _rel(d.cpu().numpy()[idx], O.decimated(S_h[idx], taps_h, K)),
                         "workload": "eq. (7) on 4096 blocks K=128 M=15: forward (N -> K) + adjoint (K -> N)"}
-    del S, taps, d, db, sb
+    del S, taps, d, db, sb, dsets
 
     # ---- differentiation workload: forward + adjoint with the shared tap gradient
     cfg = W.CONFIGS["differentiation"]
@@ -370,10 +374,14 @@ def extras(T, W, args):
     sb = torch.empty_like(S)
     tb = torch.empty(N, dtype=torch.float32, device=dev)
 
-    df = T.bind_forward(S, taps, K, M, y)
-    da = T.bind_adjoint(yb, taps, K, M, sb, coeffs=S, taps_bar=tb)
+    # two buffer sets (0.6 GB each), alternated so that no step re-reads cached data
+    S2, yb2 = S.clone(), yb.clone()
+    y2, sb2 = torch.empty_like(S), torch.empty_like(S)
+    dcalls = [(T.bind_forward(Si, taps, K, M, yi), T.bind_adjoint(ybi, taps, K, M, sbi, coeffs=Si, taps_bar=tb))
+              for (Si, yi, ybi, sbi) in ((S, y, yb, sb), (S2, y2, yb2, sb2))]
 
     def dstep(i):
+        df, da = dcalls[i % 2]
         df()
         da()
 
