@@ -136,6 +136,8 @@ __global__ void __launch_bounds__(TB) decimated_kernel(DecArgs a)
 #pragma unroll
             for (int i = 0; i < ITK; ++i)
                 if (ITK * TB == K || tid + i * TB < K) u[i] = conj(L[tid + i * TB]);
+            // non-temporal stores: the N outputs are not read again soon, and keeping them out
+            // of the caches leaves less to write back under the next launch's reads
             for (int r = 0; r < M; ++r) {
                 float t[ITK];
 #pragma unroll
@@ -143,7 +145,7 @@ __global__ void __launch_bounds__(TB) decimated_kernel(DecArgs a)
 #pragma unroll
                 for (int i = 0; i < ITK; ++i)
                     if (ITK * TB == K || tid + i * TB < K)
-                        st_c(scale(u[i], t[i]), ro, uint32_t(tid + i * TB + r * K) * CB, 0);
+                        st_c<2>(scale(u[i], t[i]), ro, uint32_t(tid + i * TB + r * K) * CB, 0);
             }
         }
     }
