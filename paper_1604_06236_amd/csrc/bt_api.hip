@@ -268,7 +268,7 @@ static int check_common(const void *in, const float *taps, const void *out, int6
 
 static size_t fused_ws_bytes(int64_t rows, int64_t N)
 {
-    const int64_t nch = (rows + 63) / 64;
+    const int64_t nch = rows_reduce_chunks(rows);
     return size_t(rows + (nch > 1 ? nch : 0)) * N * sizeof(float);
 }
 
@@ -276,7 +276,7 @@ static size_t plain_ws_bytes(int64_t nblocks, int64_t N, bool tapgrad, bool shar
 {
     size_t b = size_t(2) * nblocks * N * sizeof(c32);
     if (tapgrad && shared) {
-        const int64_t nch = (nblocks + 63) / 64;
+        const int64_t nch = rows_reduce_chunks(nblocks);
         b += size_t(nblocks + (nch > 1 ? nch : 0)) * N * sizeof(float);
     }
     return b;

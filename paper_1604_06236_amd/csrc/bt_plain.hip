@@ -137,7 +137,8 @@ __global__ void rows_reduce_kernel(const float *part, int64_t rows, int64_t n, i
     const int64_t r0 = int64_t(blockIdx.y) * chunk;
     const int64_t r1 = (r0 + chunk < rows) ? r0 + chunk : rows;
     float acc = 0.0f;
-    for (int64_t r = r0; r < r1; ++r) acc += part[r * n + k];
+#pragma unroll 8
+    for (int64_t r = r0; r < r1; ++r) acc += part[r * n + k];     // loads issued ahead, adds in row order
     out[int64_t(blockIdx.y) * n + k] = acc;
 }
 
@@ -179,10 +180,11 @@ hipError_t plain_run(const PlainArgs &a, const c32 *in, c32 *ws0, c32 *ws1, floa
 hipError_t rows_reduce(const float *part, int64_t rows, int64_t n, float *scratch, float *out,
                        hipStream_t s)
 {
-    // two fixed-order stages: chunks of 64 rows, then the chunk sums
+    // two fixed-order stages: chunks of ROWS_REDUCE_CHUNK rows (many workgroups, short
+    // loops), then the chunk sums
     const int T = 256;
-    const int64_t chunk = 64;
-    const int64_t nch = (rows + chunk - 1) / chunk;
+    const int64_t chunk = ROWS_REDUCE_CHUNK;
+    const int64_t nch = rows_reduce_chunks(rows);
     if (nch <= 1) {
         hipLaunchKernelGGL(rows_reduce_kernel, dim3(grid_for(n, T), 1), dim3(T), 0, s, part, rows, n,
                            rows > 0 ? rows : 1, out);

@@ -29,8 +29,13 @@ struct PlainArgs {
 hipError_t plain_run(const PlainArgs &a, const c32 *in, c32 *ws0, c32 *ws1, float *tg_part,
                      hipStream_t s);
 
+// rows per first-stage chunk of rows_reduce, and the number of chunks (the chunk sums
+// go to the scratch rows when there are two or more)
+constexpr int64_t ROWS_REDUCE_CHUNK = 16;
+inline int64_t rows_reduce_chunks(int64_t rows) { return (rows + ROWS_REDUCE_CHUNK - 1) / ROWS_REDUCE_CHUNK; }
+
 // out[k] = sum_{r < rows} part[r*n + k], fixed order; `scratch` holds
-// ceil(rows/64)*n floats
+// rows_reduce_chunks(rows)*n floats
 hipError_t rows_reduce(const float *part, int64_t rows, int64_t n, float *scratch, float *out,
                        hipStream_t s);
 
