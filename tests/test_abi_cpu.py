@@ -94,6 +94,10 @@ def test_workspace_sizes_host_only(lib):
     assert lib.transform_workspace_size(10, 16, 5, 0, 3, 0) == 2 * 10 * 80 * 8
     assert lib.transform_workspace_size(10, 16, 5, 0, 3, 1) == 2 * 10 * 80 * 8 + 10 * 80 * 4
     assert lib.transform_workspace_size(0, 16, 5, 0, 3, 1) == 0
+    # more than one 16-row chunk: the partial rows plus one row of chunk sums per chunk
+    assert lib.transform_workspace_size(100, 16, 5, 0, 3, 1) == 2 * 100 * 80 * 8 + (100 + 7) * 80 * 4
+    assert lib.transform_workspace_size(16, 16, 5, 0, 3, 1) == 2 * 16 * 80 * 8 + 16 * 80 * 4
+    assert lib.transform_workspace_size(17, 16, 5, 0, 3, 1) == 2 * 17 * 80 * 8 + (17 + 2) * 80 * 4
 
 
 def test_adjacent_buffers_are_not_overlap(lib):
