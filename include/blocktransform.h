@@ -201,7 +201,14 @@ int transform_save_schedule(const char *json_path);
  * points live at complex offset x_off[b] of the flat arrays and its taps at
  * float offset tap_off[b] (per-block taps only).  The plan sorts the blocks
  * by cost into a work list that one persistent kernel drains through an
- * atomic queue.  K_b, M_b follow the uniform limits, with N_b = K_b M_b <= 16384.
+ * atomic queue.  Supported classes: K_b in {64, 128, 256, 512, 1024} and
+ * M_b in {3, 5, 7, 9, 15} (25 compiled classes); any other (K_b, M_b) makes
+ * plan creation return TF_EUNSUPPORTED.
+ * Concurrency: forward, inverse, adjoint and adjoint with tap gradient each
+ * drain their own queue counter, so different directions of one plan may run
+ * on different streams at once; two executions of the same direction of one
+ * plan must not overlap (they would share one queue): use one plan per stream
+ * for that.
  */
 typedef struct tf_ragged_plan_s *tf_ragged_plan;
 

@@ -252,17 +252,18 @@ static int check_common(const void *in, const float *taps, const void *out, int6
                         int32_t K, int32_t M, int64_t tap_stride, int32_t compute)
 {
     if (!supported_km(K, M)) return TF_EUNSUPPORTED;
-    if (compute != TF_FP32 && compute != TF_PLAIN_FP32) {
-        if (compute == TF_SPLIT_BF16 || compute == TF_SPLIT_FP16) return split_supported(K, M, compute);
-        return TF_EUNSUPPORTED;
-    }
+    const bool split = compute == TF_SPLIT_BF16 || compute == TF_SPLIT_FP16;
+    if (compute != TF_FP32 && compute != TF_PLAIN_FP32 && !split) return TF_EUNSUPPORTED;
+    // argument checks first, for every compute mode: no launch sees a bad pointer or size
     if (nblocks < 0) return TF_EINVAL;
     const int64_t N = int64_t(K) * M;
     if (tap_stride != 0 && tap_stride != N) return TF_EINVAL;
-    if (nblocks == 0) return TF_OK;
-    if (!in || !out || !taps) return TF_EINVAL;
-    if (!aligned(in, 8) || !aligned(out, 8) || !aligned(taps, 4)) return TF_EINVAL;
-    if (overlap(in, out, size_t(nblocks) * N * 8)) return TF_EINVAL;
+    if (nblocks > 0) {
+        if (!in || !out || !taps) return TF_EINVAL;
+        if (!aligned(in, 8) || !aligned(out, 8) || !aligned(taps, 4)) return TF_EINVAL;
+        if (overlap(in, out, size_t(nblocks) * N * 8)) return TF_EINVAL;
+    }
+    if (split) return split_supported(K, M, compute);
     return TF_OK;
 }
 

@@ -466,6 +466,9 @@ __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
         const rsrc_t ro = rs_cplx(a.out, g);
         const rsrc_t rt = rs_taps(g);
         const uint32_t tb = shared_taps ? 0u : boff;
+        // this thread's block slot holds a block of the batch (the last group may be partial;
+        // the taps of empty slots read as 0 and must not count as zero taps)
+        const bool bvalid = uint32_t(bi) < group_blocks(g);
         rsrc_t rx = ro, rg = ro;
         if constexpr (TG != 0) {
             rx = rs_cplx(a.aux, g);
@@ -487,7 +490,7 @@ __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
                             else st_f(tg, rg, (boff + j) * FB, r * NB0 * FB);
                         }
                         if constexpr (SIDE == SIDE_IN) {
-                            zero_tap |= (t0[i][r] == 0.0f);
+                            zero_tap |= bvalid && (t0[i][r] == 0.0f);
                             v[r] = scale(x0[i][r], filter_factor(t0[i][r], a.div, Nf));
                         } else {
                             v[r] = conj(x0[i][r]);
@@ -505,7 +508,7 @@ __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
                         }
                         if constexpr (SIDE == SIDE_OUT) {
                             const float t = ld_f(rt, (tb + j) * FB, r * NB0 * FB);
-                            zero_tap |= (t == 0.0f);
+                            zero_tap |= bvalid && (t == 0.0f);
                             w = scale(w, filter_factor(t, a.div, Nf));
                         }
                         st_c(w, ro, (boff + j) * CB, r * NB0 * CB);
@@ -517,7 +520,7 @@ __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
             // ---- pass 0 on the fetched operands: filter, length-R0 DFT (no twiddle, Ns = 1)
             if constexpr (SIDE == SIDE_IN && TG != TG_IN_)
                 tap_factors(t0, a.div, Nf, zero_tap,
-                            [&](int i) { return FULL0 || MP::template j<0>(tid, i) < NB0; });
+                            [&](int i) { return bvalid && (FULL0 || MP::template j<0>(tid, i) < NB0); });
             c32 v0[IT0][R0];
 #pragma unroll
             for (int i = 0; i < IT0; ++i) {
@@ -530,7 +533,7 @@ __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
                             const float tg = -(x0[i][r].x * s.x + x0[i][r].y * s.y) / t0[i][r];
                             if (shared_taps) acc[i * R0 + r] += tg;
                             else st_f(tg, rg, (boff + j) * FB, r * NB0 * FB);
-                            zero_tap |= (t0[i][r] == 0.0f);
+                            zero_tap |= bvalid && (t0[i][r] == 0.0f);
                             v0[i][r] = scale(x0[i][r], filter_factor(t0[i][r], a.div, Nf));
                         } else if constexpr (SIDE == SIDE_IN) {
                             v0[i][r] = scale(x0[i][r], t0[i][r]);
@@ -576,7 +579,7 @@ __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
             // ---- last pass: LDS -> registers -> twiddle -> DFT_RL -> HBM
             if constexpr (SIDE == SIDE_OUT)
                 tap_factors(tl, a.div, Nf, zero_tap,
-                            [&](int i) { return FULLL || MP::template j<NP - 1>(tid, i) < NBL; });
+                            [&](int i) { return bvalid && (FULLL || MP::template j<NP - 1>(tid, i) < NBL); });
             constexpr int SLOTL = TwSlots<PL, TB, OPT>::off(NP - 1);
             constexpr int STEP = PAIRL ? 2 : 1;
 #pragma unroll
@@ -643,8 +646,6 @@ __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
     }
 }
 
-// sum of `rows` partial rows of length n: out[k] = sum_r part[r*n + k] (fixed order)
-__global__ void tapgrad_reduce_kernel(const float *part, int64_t rows, int64_t n, float *out);
 
 // ------------------------------------------------------------------ registry entry
 typedef hipError_t (*fused_launch_fn)(const FusedArgs &, unsigned grid, hipStream_t);

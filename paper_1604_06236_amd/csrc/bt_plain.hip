@@ -128,18 +128,22 @@ __global__ void plain_copy_out_kernel(PlainArgs a, const c32 *U, float *tg_part)
     }
 }
 
-// tap gradient rows -> partial sums: part2[c][k] = sum_{r in chunk c} part[r][k]
+// tap gradient rows -> partial sums: part2[c][k] = sum_{r in chunk c} part[r][k]; the
+// chunks are strided over gridDim.y (at most 65535), so any row count is covered
 __global__ void rows_reduce_kernel(const float *part, int64_t rows, int64_t n, int64_t chunk,
                                    float *out)
 {
     const int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (k >= n) return;
-    const int64_t r0 = int64_t(blockIdx.y) * chunk;
-    const int64_t r1 = (r0 + chunk < rows) ? r0 + chunk : rows;
-    float acc = 0.0f;
+    const int64_t nch = (rows + chunk - 1) / chunk;
+    for (int64_t c = blockIdx.y; c < nch; c += gridDim.y) {
+        const int64_t r0 = c * chunk;
+        const int64_t r1 = (r0 + chunk < rows) ? r0 + chunk : rows;
+        float acc = 0.0f;
 #pragma unroll 8
-    for (int64_t r = r0; r < r1; ++r) acc += part[r * n + k];     // loads issued ahead, adds in row order
-    out[int64_t(blockIdx.y) * n + k] = acc;
+        for (int64_t r = r0; r < r1; ++r) acc += part[r * n + k];   // loads issued ahead, adds in row order
+        out[c * n + k] = acc;
+    }
 }
 
 static unsigned grid_for(int64_t work, int threads)
@@ -190,7 +194,8 @@ hipError_t rows_reduce(const float *part, int64_t rows, int64_t n, float *scratc
                            rows > 0 ? rows : 1, out);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(rows_reduce_kernel, dim3(grid_for(n, T), unsigned(nch)), dim3(T), 0, s, part,
+    const unsigned gy = unsigned(nch < 65535 ? nch : 65535);
+    hipLaunchKernelGGL(rows_reduce_kernel, dim3(grid_for(n, T), gy), dim3(T), 0, s, part,
                        rows, n, chunk, scratch);
     hipLaunchKernelGGL(rows_reduce_kernel, dim3(grid_for(n, T), 1), dim3(T), 0, s,
                        (const float *)scratch, nch, n, nch, out);

@@ -544,7 +544,7 @@ extern "C" int transform_ragged_plan_create_ex(const int32_t *K, const int32_t *
     if (!rc) rc = upload_vec(sorted, &p->items);
     if (!rc) rc = upload_vec(tw, &p->tw);
     if (!rc) rc = upload_vec(tw_off, &p->tw_off);
-    if (!rc) rc = upload_vec(std::vector<int>{0}, &p->counter);
+    if (!rc) rc = upload_vec(std::vector<int>{0, 0, 0, 0}, &p->counter);   // one queue per direction
     // persistent grid: the resident capacity for this LDS size, per kernel variant
     int cus = 0;
     if (!rc && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess)
@@ -585,13 +585,16 @@ static hipError_t ragged_launch(tf_ragged_plan p, int dir, const RaggedArgs &a, 
     const int side = dir == 0 ? SIDE_IN : SIDE_OUT;
     const bool tg = a.tapbar != nullptr;
     const int v = dir == 0 ? 0 : (tg ? 2 : 1);
-    hipLaunchKernelGGL(ragged_reset_kernel, dim3(1), dim3(1), 0, s, a.counter);
+    const int q = dir + (tg ? 1 : 0);     // forward, inverse, adjoint, adjoint with tap gradient
+    hipLaunchKernelGGL(ragged_reset_kernel, dim3(1), dim3(1), 0, s, a.counter + q);
+    RaggedArgs av = a;
+    av.counter = a.counter + q;
     if (side == SIDE_IN)
-        hipLaunchKernelGGL((ragged_kernel<SIDE_IN, false>), dim3(p->grid[v]), dim3(RT), p->max_lds, s, a);
+        hipLaunchKernelGGL((ragged_kernel<SIDE_IN, false>), dim3(p->grid[v]), dim3(RT), p->max_lds, s, av);
     else if (tg)
-        hipLaunchKernelGGL((ragged_kernel<SIDE_OUT, true>), dim3(p->grid[v]), dim3(RT), p->max_lds, s, a);
+        hipLaunchKernelGGL((ragged_kernel<SIDE_OUT, true>), dim3(p->grid[v]), dim3(RT), p->max_lds, s, av);
     else
-        hipLaunchKernelGGL((ragged_kernel<SIDE_OUT, false>), dim3(p->grid[v]), dim3(RT), p->max_lds, s, a);
+        hipLaunchKernelGGL((ragged_kernel<SIDE_OUT, false>), dim3(p->grid[v]), dim3(RT), p->max_lds, s, av);
     return hipGetLastError();
 }
 

@@ -65,6 +65,24 @@ def test_host_validation(lib):
                                  None) == nat.TF_EINVAL
 
 
+@pytest.mark.parametrize("compute", [nat.TF_SPLIT_BF16, nat.TF_SPLIT_FP16])
+def test_host_validation_split_modes(lib, compute):
+    """The split-precision modes run the same argument checks before any launch."""
+    K, M = 1024, 15
+    assert _fwd(lib, 4, K, M, compute=compute, ptr=0) == nat.TF_EINVAL       # null pointers
+    assert _fwd(lib, 4, K, M, ts=7, compute=compute) == nat.TF_EINVAL        # tap stride
+    assert _fwd(lib, -1, K, M, compute=compute) == nat.TF_EINVAL             # negative count
+    assert _fwd(lib, 4, K, M, ptr=12, compute=compute) == nat.TF_EINVAL      # misaligned
+    p = ctypes.c_void_p(1 << 20)
+    t = ctypes.c_void_p(1 << 32)
+    assert lib.transform_forward(p, t, p, 4, K, M, 0, compute, None, 0, None) == nat.TF_EINVAL
+    assert lib.transform_adjoint(p, t, None, ctypes.c_void_p((1 << 20) + 64), None, 4, K, M, 0,
+                                 compute, None, 0, None) == nat.TF_EINVAL
+    # a size the split path does not cover stays unsupported once the arguments are valid
+    assert _fwd(lib, 4, 128, 15, compute=compute) == nat.TF_EUNSUPPORTED
+    assert _fwd(lib, 0, K, M, compute=compute, ptr=0) == nat.TF_OK           # empty batch
+
+
 def test_schedule_registry(lib, tmp_path):
     from paper_1604_06236_amd import transform as T
     for K in (1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024):

@@ -264,6 +264,34 @@ def test_zero_tap_sets_status(T):
     assert int(st.item()) == 0
 
 
+@pytest.mark.parametrize("K,M", [(16, 5), (128, 15), (1, 3), (64, 1)])
+def test_per_block_taps_partial_group_leaves_status_clear(T, K, M):
+    """Per-block nonzero taps with a batch that leaves the last block group partial (37 blocks):
+    the empty block slots read zero taps, which must not count as zero taps.  Also a zero tap in
+    the last block alone is still reported."""
+    import torch
+    B = 37
+    N = K * M
+    S, taps = _inputs(B, K, M, seed=37 + K, shared=False)
+    y = W.cn01(np.random.default_rng(K + M), (B, N)).astype(np.complex64)
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for i, sched in enumerate(T.schedules(K, M)):
+        print(f"case status K={K} M={M} idx={i}", flush=True)
+        T.select_schedule(K, M, i)
+        try:
+            st.zero_()
+            out = _host(T.transform_inverse(_dev(y), _dev(taps), K, M, status=st))
+            assert int(st.item()) == 0, (K, M, i)
+            assert rel_l2(out, O.inverse(y, taps)) < TOL
+            t2 = taps.copy()
+            t2[B - 1, N - 1] = 0.0
+            st.zero_()
+            T.transform_inverse(_dev(y), _dev(t2), K, M, status=st)
+            assert int(st.item()) == 1, (K, M, i)
+        finally:
+            T.select_schedule(K, M, -1)
+
+
 def test_empty_and_errors(T):
     import torch
     from paper_1604_06236_amd._native import TransformError
@@ -291,26 +319,51 @@ def test_determinism(T):
     assert np.array_equal(_host(t1).view(np.uint32), _host(t2).view(np.uint32))
 
 
+def _samples_input(cfg, shape):
+    """Seeded samples for the inverse and the adjoint, a stream of their own."""
+    rng = W.rng_streams(W.CONFIGS[cfg].seed + 100, 1)[0]
+    return W.cn01(rng, shape).astype(np.complex64)
+
+
+# batches whose O(N^2) sums take seconds on the host threads are checked block by block
+# against them; larger ones against the FFT form of the oracle (pinned to the sums) on every
+# block, plus a seeded sample against the sums
+SUMS_LIMIT = 5e10
+
+
 @pytest.mark.parametrize("cfg", ["plain_cpu", "plain_gpu", "differentiation", "precision"])
 def test_standard_config_full_size(T, cfg):
-    """Full-size batches in the benchmark's launch configuration: a seeded sample
-    of blocks against the oracle, every block through the round trip."""
+    """Full-size batches in the benchmark's launch configuration, every block of every
+    direction against the oracle (forward, inverse, adjoint with the reduced tap
+    gradient), batch and worst-block relative L2 <= 1e-5."""
+    from oracle import fftref as F
     c = W.CONFIGS[cfg]
     S, taps = W.make_uniform(cfg)
     K, M = c.K, c.M
-    print(f"case full {cfg} B={S.shape[0]}", flush=True)
-    y = T.transform_forward(_dev(S), _dev(taps), K, M)
-    yh = _host(y)
-    idx = np.sort(np.random.default_rng(0).choice(S.shape[0], size=min(64, S.shape[0]), replace=False))
-    idx = np.unique(np.concatenate([idx, [0, S.shape[0] - 1]]))
-    ref = O.forward(S[idx], taps)
-    assert rel_l2(yh[idx], ref) < TOL and block_rel_l2(yh[idx], ref) < TOL
-    back = _host(T.transform_inverse(y, _dev(taps), K, M))
-    assert rel_l2(back, S) < TOL
-    sb, tb = T.transform_adjoint(y, _dev(taps), K, M, coeffs=_dev(S), want_taps_bar=True)
-    sb_ref, _ = O.adjoint(yh[idx], taps, S[idx])
-    assert rel_l2(_host(sb)[idx], sb_ref) < TOL
-    # full tap gradient: Lambdabar_n = sum_b Re(conj(S) W), with W = DFT(y) = N taps S here
-    # (since y = T S), so Lambdabar = N taps sum_b |S_n|^2 -- a property that holds at any size
+    B, N = S.shape
+    yin = _samples_input(cfg, (B, N))
+    print(f"case full {cfg} B={B} N={N}", flush=True)
+    dS, dt, dy = _dev(S), _dev(taps), _dev(yin)
+    y = _host(T.transform_forward(dS, dt, K, M))
+    back = _host(T.transform_inverse(dy, dt, K, M))
+    sb, tb = T.transform_adjoint(dy, dt, K, M, coeffs=dS, want_taps_bar=True)
+    sb, tb = _host(sb), _host(tb)
+    if B * N * N <= SUMS_LIMIT:
+        y_ref, S_ref = O.forward(S, taps), O.inverse(yin, taps)
+        sb_ref, tb_ref = O.adjoint(yin, taps, S)
+    else:
+        idx = np.unique(np.concatenate([np.random.default_rng(0).choice(B, 62, replace=False), [0, B - 1]]))
+        assert rel_l2(y[idx], O.forward(S[idx], taps)) < TOL
+        assert rel_l2(back[idx], O.inverse(yin[idx], taps)) < TOL
+        assert rel_l2(sb[idx], O.adjoint(yin[idx], taps)[0]) < TOL
+        y_ref, S_ref = F.forward(S, taps), F.inverse(yin, taps)
+        sb_ref, tb_ref = F.adjoint(yin, taps, S)
+    for got, ref in ((y, y_ref), (back, S_ref), (sb, sb_ref)):
+        assert rel_l2(got, ref) < TOL and block_rel_l2(got, ref) < TOL
+    assert rel_l2(tb, tb_ref) < TOL
+    # the tap gradient at ybar = forward(S): Lambdabar_n = sum_b Re(conj(S) W) with
+    # W = DFT(T S) = N taps S, so Lambdabar = N taps sum_b |S_n|^2 (a closed form of the inputs)
+    _, tb_fs = T.transform_adjoint(T.transform_forward(dS, dt, K, M), dt, K, M, coeffs=dS,
+                                   want_taps_bar=True)
     expect = K * M * taps.astype(np.float64) * np.sum(np.abs(S.astype(np.complex128)) ** 2, axis=0)
-    assert rel_l2(_host(tb), expect) < TOL
+    assert rel_l2(_host(tb_fs), expect) < TOL

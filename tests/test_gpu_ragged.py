@@ -53,6 +53,9 @@ def test_ragged_forward_inverse_adjoint(T, use_graph):
     back = _host(plan.execute("inverse", y, dt, use_graph=use_graph))
     assert rel_l2(back, S.astype(np.complex128)) < TOL
     yb = W.cn01(np.random.default_rng(4), lay.total).astype(np.complex64)
+    inv_ref = O.inverse_ragged(lay.N, lay.x_off, lay.tap_off, yb, taps)
+    inv = _host(plan.execute("inverse", _dev(yb), dt, use_graph=use_graph))
+    assert rel_l2(inv, inv_ref) < TOL and per_block_max(inv, inv_ref, lay) < TOL
     sb_ref, tb_ref = O.adjoint_ragged(lay.N, lay.x_off, lay.tap_off, yb, taps, S)
     sb, tb = plan.execute("adjoint", _dev(yb), dt, aux=dS, want_taps_bar=True, use_graph=use_graph)
     assert rel_l2(_host(sb), sb_ref) < TOL
@@ -115,24 +118,42 @@ def test_ragged_unsorted_offsets_and_gaps(T):
     plan.close()
 
 
-def test_ragged_full_batch_properties(T):
-    """The full 10,000-block batch: sampled blocks against the oracle, every block
-    through the inverse round trip."""
+def test_ragged_full_batch(T):
+    """The full 10,000-block batch in the benchmark's launch (HIP graph replay), every block of
+    every direction against the FFT form of the oracle, 40 seeded blocks against the O(N^2)
+    sums, and every block through the inverse round trip."""
+    from oracle import fftref as F
     lay, S, taps = W.make_ragged("ragged")
     print(f"case ragged full blocks={lay.K.size} points={lay.total}", flush=True)
+    args = (lay.N, lay.x_off, lay.tap_off)
+    yb = W.cn01(W.rng_streams(W.CONFIGS["ragged"].seed + 100, 1)[0], lay.total).astype(np.complex64)
     plan = T.RaggedPlan(lay.K, lay.M, lay.x_off, lay.tap_off, lay.total)
-    dS, dt = _dev(S), _dev(taps)
-    y = plan.execute("forward", dS, dt)
-    back = _host(plan.execute("inverse", y, dt))
-    assert rel_l2(back, S.astype(np.complex128)) < TOL
+    dS, dt, dyb = _dev(S), _dev(taps), _dev(yb)
+    y = plan.execute("forward", dS, dt, use_graph=True)
+    yh = _host(y)
+    inv = _host(plan.execute("inverse", dyb, dt, use_graph=True))
+    sb, tb = plan.execute("adjoint", dyb, dt, aux=dS, want_taps_bar=True, use_graph=True)
+    sb, tb = _host(sb), _host(tb).astype(np.float64)
+    sb2 = _host(plan.execute("adjoint", dyb, dt, use_graph=True))
+    back = _host(plan.execute("inverse", y, dt, use_graph=True))
+    y_ref = F.forward_ragged(*args, S, taps)
+    inv_ref = F.inverse_ragged(*args, yb, taps)
+    sb_ref, tb_ref = F.adjoint_ragged(*args, yb, taps, S)
+    for got, ref in ((yh, y_ref), (inv, inv_ref), (sb, sb_ref), (sb2, sb_ref)):
+        assert rel_l2(got, ref) < TOL and per_block_max(got, ref, lay) < TOL
+    assert float(np.linalg.norm(tb - tb_ref) / np.linalg.norm(tb_ref)) < TOL
+    assert rel_l2(back, S.astype(np.complex128)) < TOL and per_block_max(back, S.astype(np.complex128), lay) < TOL
+    # a seeded sample against the O(N^2) sums
     idx = np.sort(np.random.default_rng(1).choice(lay.K.size, 40, replace=False))
     sub = lay.subset(idx)
-    yh = _host(y)
-    Ssub = np.concatenate([S[int(lay.x_off[b]):int(lay.x_off[b] + lay.N[b])] for b in idx])
+
+    def pick(x):
+        return np.concatenate([x[int(lay.x_off[b]):int(lay.x_off[b] + lay.N[b])] for b in idx])
     tsub = np.concatenate([taps[int(lay.tap_off[b]):int(lay.tap_off[b] + lay.N[b])] for b in idx])
-    ysub = np.concatenate([yh[int(lay.x_off[b]):int(lay.x_off[b] + lay.N[b])] for b in idx])
-    ref = O.forward_ragged(sub.N, sub.x_off, sub.tap_off, Ssub, tsub)
-    assert rel_l2(ysub, ref) < TOL
+    sargs = (sub.N, sub.x_off, sub.tap_off)
+    assert rel_l2(pick(yh), O.forward_ragged(*sargs, pick(S), tsub)) < TOL
+    assert rel_l2(pick(inv), O.inverse_ragged(*sargs, pick(yb), tsub)) < TOL
+    assert rel_l2(pick(sb), O.adjoint_ragged(*sargs, pick(yb), tsub)[0]) < TOL
     plan.close()
 
 

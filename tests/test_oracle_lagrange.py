@@ -48,6 +48,43 @@ def test_mu_and_damping_invert_each_other():
             assert np.isclose(L.mu_of(L.damping_for(mu, eta, P), eta, P), mu, rtol=1e-12)
 
 
+def test_mu_is_the_last_kept_coefficient_eq49():
+    """eq. (49)'s truncation ratio is the magnitude of the last coefficient kept in the
+    series eq. (41)/(42) at R = eta P, |g_{R-1}| (pinned through log_taps, itself pinned
+    to the closed form below).  Using eta P instead of eta P - 1 fails this at 1e-12."""
+    for eta, P in ((1, 64), (6, 1024), (15, 1024), (2, 16)):
+        for mu in (1e-4, 1e-7, 1e-12):
+            a = L.damping_for(mu, eta, P)
+            g = L.log_taps(eta * P, a)
+            assert np.isclose(abs(g[-1]), mu, rtol=1e-12), (eta, P, mu)
+            assert np.isclose(L.mu_of(a, eta, P), abs(g[-1]), rtol=1e-12)
+
+
+def test_package_damping_matches_the_pinned_oracle():
+    """Host logic: the package's eq. (49) inversion equals the oracle's pinned one."""
+    from paper_1604_06236_amd import nufft as NU
+    for eta, P in ((1, 64), (6, 1024), (2, 256)):
+        for mu in (1e-3, 1e-7):
+            assert np.isclose(NU.damping_for(mu, eta, P), L.damping_for(mu, eta, P), rtol=1e-14)
+
+
+def test_damping_sets_the_series_truncation_error():
+    """With a = damping_for(mu), the series truncated at R = eta P misses log(1 - e^{j2pi(t+ja)})
+    by the tail sum_{p >= R} e^{-2 pi p a}/p: at t = 0 it lies between the first omitted term,
+    mu e^{-2 pi a} (R-1)/R, and the geometric bound mu e^{-2 pi a}/(1 - e^{-2 pi a})."""
+    for eta, P, mu in ((2, 64, 1e-8), (1, 128, 1e-5), (4, 32, 1e-10)):
+        R = eta * P
+        a = L.damping_for(mu, eta, P)
+        g = L.log_taps(R, a)
+        t = np.linspace(0, 1, 64, endpoint=False)
+        series = np.exp(2j * np.pi * np.outer(t, np.arange(R))) @ g
+        closed = np.log(1.0 - np.exp(2j * np.pi * (t + 1j * a)))
+        err = np.abs(series - closed)
+        q = np.exp(-2 * np.pi * a)
+        assert err.max() <= mu * q / (1 - q) * (1 + 1e-6) + 1e-14, (eta, P, mu)
+        assert err[0] >= mu * q * (R - 1) / R * (1 - 1e-6), (eta, P, mu)
+
+
 # ------------------------------------------------------------ series and closed forms
 def test_log_series_eq42():
     """log(1 - exp(j 2 pi (t + j a))) equals the series with the g coefficients."""

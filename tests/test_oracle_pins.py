@@ -241,3 +241,38 @@ def test_inverse_pins_reject_mutant(mutant):
 def test_adjoint_pin_rejects_mutant(mutant):
     with pytest.raises(AssertionError):
         pins.pin_adjoint(fwd, mutant)
+
+
+# ----------------------------------------------------------------- FFT form of the oracle
+def test_fft_form_matches_the_plain_sums():
+    """oracle/fftref.py (numpy FFT as its one library step) equals the O(N^2) oracle on
+    uniform batches with shared and per-block taps, forward, inverse and adjoint."""
+    from oracle import fftref as F
+    from paper_1604_06236_amd import workloads as W
+    rng = np.random.default_rng(21)
+    for B, N in ((3, 80), (2, 1920), (4, 48), (1, 1)):
+        S = W.cn01(rng, (B, N))
+        y = W.cn01(rng, (B, N))
+        for taps in (rng.uniform(0.5, 1.5, N), rng.uniform(0.5, 1.5, (B, N))):
+            assert pins.rel_l2(F.forward(S, taps), O.forward(S, taps)) < 1e-12
+            assert pins.rel_l2(F.inverse(y, taps), O.inverse(y, taps)) < 1e-12
+            sb, tb = F.adjoint(y, taps, S)
+            sb0, tb0 = O.adjoint(y, taps, S)
+            assert pins.rel_l2(sb, sb0) < 1e-12
+            assert np.linalg.norm(tb - tb0) <= 1e-12 * np.linalg.norm(tb0)
+
+
+def test_fft_form_ragged_matches_the_plain_sums():
+    from oracle import fftref as F
+    from paper_1604_06236_amd import workloads as W
+    lay, S, taps = W.make_ragged("ragged", nblocks=30)
+    y = W.cn01(np.random.default_rng(5), lay.total)
+    args = (lay.N, lay.x_off, lay.tap_off)
+    assert pins.rel_l2(F.forward_ragged(*args, S, taps), O.forward_ragged(*args, S, taps)) < 1e-12
+    assert pins.rel_l2(F.inverse_ragged(*args, y, taps), O.inverse_ragged(*args, y, taps)) < 1e-12
+    sb, tb = F.adjoint_ragged(*args, y, taps, S)
+    sb0, tb0 = O.adjoint_ragged(*args, y, taps, S)
+    assert pins.rel_l2(sb, sb0) < 1e-12
+    assert np.linalg.norm(tb - tb0) <= 1e-12 * np.linalg.norm(tb0)
+    sb1, none = F.adjoint_ragged(*args, y, taps)
+    assert none is None and pins.rel_l2(sb1, sb0) < 1e-12
