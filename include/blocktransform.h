@@ -121,6 +121,27 @@ int transform_adjoint(const void *samples_bar, const float *taps, const void *co
                       void *stream);
 
 /*
+ * transform_adjoint_noalloc -- transform_adjoint (FP32) for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  Same arguments and results as transform_adjoint with compute = TF_FP32, but
+ * no workspace: the shared tap gradient's partial rows live in a device array of the
+ * library (transform_noalloc_scratch_bytes(), 16 MiB, one copy per GPU, held until the
+ * process ends); the launch grid is capped so that they fit, which can change the order of
+ * the partial sums against transform_adjoint (results differ by rounding only).  Calls no
+ * allocating routine.  All calls on one GPU share that array: calls that overlap in time on
+ * one GPU (two streams, two threads) race and must not be issued; calls on one stream are
+ * ordered and safe.  Errors as transform_adjoint; TF_EWORKSPACE if even a one-workgroup
+ * grid's partial rows would not fit (cannot happen for N <= 16384).
+ */
+int transform_adjoint_noalloc(const void *samples_bar, const float *taps, const void *coeffs,
+                              void *coeffs_bar, float *taps_bar,
+                              int64_t nblocks, int32_t K, int32_t M, int64_t tap_stride,
+                              void *stream);
+
+/* Size in bytes of the device array transform_adjoint_noalloc uses (per GPU). */
+size_t transform_noalloc_scratch_bytes(void);
+
+/*
  * transform_inverse_adjoint -- the Hermitian of the inverse, and its filter gradient
  * (what autograd needs behind transform_inverse).
  *   ybar_u = sum_n e^{+j 2 pi n u/N} gbar_n / (N Lambda_n);

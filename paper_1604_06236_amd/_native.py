@@ -38,7 +38,7 @@ EXPORTED = (
     "nufft_workspace_size", "nufft_type5", "nufft_type4", "nufft_type5_refined", "nufft_type4_refined",
     "nudft_type1", "nudft_type2", "nufft_workspace_size_ex", "nufft_solve", "nufft_setup", "nufft_apply",
     "nfft_workspace_size",
-    "nfft_type1", "nfft_type2",
+    "nfft_type1", "nfft_type2", "transform_adjoint_noalloc", "transform_noalloc_scratch_bytes",
 )
 
 _lib = None
@@ -67,6 +67,9 @@ def load() -> ctypes.CDLL:
     lib.transform_inverse.argtypes = [vp, vp, vp, i64, i32, i32, i64, i32, vp, vp, sz, vp]
     lib.transform_adjoint.argtypes = [vp, vp, vp, vp, vp, i64, i32, i32, i64, i32, vp, sz, vp]
     lib.transform_inverse_adjoint.argtypes = [vp, vp, vp, vp, vp, i64, i32, i32, i64, i32, vp, sz, vp]
+    lib.transform_adjoint_noalloc.argtypes = [vp, vp, vp, vp, vp, i64, i32, i32, i64, vp]
+    lib.transform_noalloc_scratch_bytes.argtypes = []
+    lib.transform_noalloc_scratch_bytes.restype = sz
     lib.transform_decimated.argtypes = [vp, vp, vp, i64, i32, i32, i64, vp]
     lib.transform_decimated_adjoint.argtypes = [vp, vp, vp, i64, i32, i32, i64, vp]
     lib.transform_workspace_size.argtypes = [i64, i32, i32, i64, i32, i32]

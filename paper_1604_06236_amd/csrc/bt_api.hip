@@ -66,6 +66,7 @@ struct DeviceState {
     std::map<int, c32 *> tw;                       // entry -> twiddle table
     std::map<std::pair<int, int>, int> occ;        // (entry, kernel variant) -> workgroups per CU
     std::map<std::pair<int, int>, c32 *> roots;    // (K, M) -> N-th roots (plain path)
+    float *scratch = nullptr;                      // this device's copy of the no-alloc scratch array
 };
 static std::map<int, DeviceState> g_dev;
 
@@ -208,8 +209,16 @@ struct Geometry {
     int64_t rows;        // partial tap-gradient rows (grid * BPW)
 };
 
+static size_t fused_ws_bytes(int64_t rows, int64_t N)
+{
+    const int64_t nch = rows_reduce_chunks(rows);
+    return size_t(rows + (nch > 1 ? nch : 0)) * N * sizeof(float);
+}
+
+// ws_cap: when nonzero, the grid is also capped so that the shared tap gradient's
+// partial rows and chunk sums fit in ws_cap bytes
 static int fused_geometry(int dev, int K, int M, int64_t nblocks, int side, bool tg,
-                          bool shared_tapgrad, Geometry *g, const c32 **tw)
+                          bool shared_tapgrad, Geometry *g, const c32 **tw, size_t ws_cap = 0)
 {
     int cap = 0;
     int idx = chosen_entry(K, M, &cap);
@@ -225,6 +234,11 @@ static int fused_geometry(int dev, int K, int M, int64_t nblocks, int side, bool
     if (cap > 0 && grid > cap) grid = cap;
     if (grid > 0x7fffffff) grid = 0x7fffffff;
     if (grid < 1) grid = 1;
+    if (shared_tapgrad && ws_cap > 0) {
+        const int64_t N = int64_t(K) * M;
+        while (grid > 1 && fused_ws_bytes(grid * e.BPW, N) > ws_cap) grid = (grid + 1) / 2;
+        if (fused_ws_bytes(grid * e.BPW, N) > ws_cap) return TF_EWORKSPACE;
+    }
     g->idx = idx;
     g->grid = unsigned(grid);
     g->rows = grid * e.BPW;
@@ -267,12 +281,6 @@ static int check_common(const void *in, const float *taps, const void *out, int6
     return TF_OK;
 }
 
-static size_t fused_ws_bytes(int64_t rows, int64_t N)
-{
-    const int64_t nch = rows_reduce_chunks(rows);
-    return size_t(rows + (nch > 1 ? nch : 0)) * N * sizeof(float);
-}
-
 static size_t plain_ws_bytes(int64_t nblocks, int64_t N, bool tapgrad, bool shared)
 {
     size_t b = size_t(2) * nblocks * N * sizeof(c32);
@@ -312,7 +320,8 @@ extern "C" size_t transform_workspace_size(int64_t nblocks, int32_t K, int32_t M
 // multiplying by Lambda; tg: also compute the tap gradient into taps_bar.
 static int run(const void *in, const float *taps, void *out, const void *aux, float *taps_bar,
                int32_t *status, int64_t nblocks, int32_t K, int32_t M, int64_t tap_stride,
-               int32_t compute, int side, int div, bool tg, void *ws, size_t ws_bytes, void *stream)
+               int32_t compute, int side, int div, bool tg, void *ws, size_t ws_bytes, void *stream,
+               bool ws_caps_grid = false)
 {
     const int64_t N = int64_t(K) * M;
     const bool shared = tap_stride == 0;
@@ -359,7 +368,7 @@ static int run(const void *in, const float *taps, void *out, const void *aux, fl
 
     Geometry g{};
     const c32 *tw = nullptr;
-    rc = fused_geometry(dev, K, M, nblocks, side, tg, tg && shared, &g, &tw);
+    rc = fused_geometry(dev, K, M, nblocks, side, tg, tg && shared, &g, &tw, ws_caps_grid ? ws_bytes : 0);
     if (rc) return rc;
     float *part = nullptr;
     if (tg && shared) {
@@ -440,6 +449,64 @@ extern "C" int transform_adjoint(const void *samples_bar, const float *taps, con
     }
     return run(samples_bar, taps, coeffs_bar, coeffs, taps_bar, nullptr, nblocks, K, M, tap_stride,
                compute, SIDE_OUT, 0, taps_bar != nullptr, workspace, workspace_bytes, stream);
+}
+
+// ------------------------------------------------------------------ allocation-free adjoint
+// Scratch of transform_adjoint_noalloc: the shared tap gradient's partial rows and chunk
+// sums.  One copy per GPU, held until the process ends.  Host code never uses the name
+// itself as an address: each device's address comes from hipGetSymbolAddress.
+constexpr size_t kNoallocScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) float scratch[kNoallocScratchBytes / sizeof(float)];
+
+// this device's address of `scratch`, looked up once per device with the device current
+// (called under g_mu)
+static int noalloc_scratch(int dev, float **ptr)
+{
+    DeviceState &d = dev_state(dev);
+    if (!d.scratch) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error("hipGetSymbolAddress(scratch)", e);
+            return TF_EHIP;
+        }
+        d.scratch = static_cast<float *>(p);
+    }
+    *ptr = d.scratch;
+    return TF_OK;
+}
+
+extern "C" size_t transform_noalloc_scratch_bytes(void) { return kNoallocScratchBytes; }
+
+extern "C" int transform_adjoint_noalloc(const void *samples_bar, const float *taps, const void *coeffs,
+                                         void *coeffs_bar, float *taps_bar, int64_t nblocks, int32_t K,
+                                         int32_t M, int64_t tap_stride, void *stream)
+{
+    int rc = check_common(samples_bar, taps, coeffs_bar, nblocks, K, M, tap_stride, TF_FP32);
+    if (rc || nblocks == 0) return rc;
+    const int64_t N = int64_t(K) * M;
+    if (taps_bar) {
+        if (!coeffs || !aligned(coeffs, 8) || !aligned(taps_bar, 4)) return TF_EINVAL;
+        if (overlap(coeffs, coeffs_bar, size_t(nblocks) * N * 8)) return TF_EINVAL;
+        const size_t tb_bytes = size_t(tap_stride == 0 ? 1 : nblocks) * N * 4;
+        const size_t x_bytes = size_t(nblocks) * N * 8;
+        if (overlap2(taps_bar, tb_bytes, coeffs_bar, x_bytes) ||
+            overlap2(taps_bar, tb_bytes, samples_bar, x_bytes) ||
+            overlap2(taps_bar, tb_bytes, coeffs, x_bytes))
+            return TF_EINVAL;
+    }
+    float *ws = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        int dev = 0;
+        rc = current_device(&dev);
+        if (!rc) rc = noalloc_scratch(dev, &ws);
+    }
+    if (rc) return rc;
+    // the shared tap gradient's partial rows go to the scratch array, the grid capped so that
+    // they fit; every row is written in full by the kernel, so nothing needs clearing
+    return run(samples_bar, taps, coeffs_bar, coeffs, taps_bar, nullptr, nblocks, K, M, tap_stride,
+               TF_FP32, SIDE_OUT, 0, taps_bar != nullptr, ws, kNoallocScratchBytes, stream, true);
 }
 
 extern "C" int transform_inverse_adjoint(const void *coeffs_bar, const float *taps, const void *coeffs,
