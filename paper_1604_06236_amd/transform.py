@@ -390,3 +390,19 @@ class RaggedPlan:
             self._h, d, _ptr(x), _ptr(taps), _ptr(out), _ptr(aux), _ptr(tb), _ptr(status),
             1 if use_graph else 0, _stream(x.device)))
         return (out, tb) if want_taps_bar else out
+
+    def bind(self, direction: str, x: torch.Tensor, taps: torch.Tensor, out: torch.Tensor, *,
+             aux: Optional[torch.Tensor] = None, taps_bar: Optional[torch.Tensor] = None,
+             use_graph: bool = True) -> BoundCall:
+        """One execution with its arguments checked and marshalled once (see BoundCall)."""
+        d = self.DIRECTIONS[direction]
+        for t, name in ((x, "x"), (out, "out")):
+            if t.dtype != torch.complex64 or t.numel() != self.total_points or not t.is_contiguous():
+                raise ValueError(f"{name} must be contiguous complex64 [{self.total_points}]")
+        if taps.dtype != torch.float32 or not taps.is_contiguous():
+            raise ValueError("taps must be contiguous float32")
+        if taps_bar is not None and (d != 2 or aux is None):
+            raise ValueError("the tap gradient is an adjoint output and needs aux = S")
+        return BoundCall("transform_ragged_execute",
+                         (self._h, d, _ptr(x), _ptr(taps), _ptr(out), _ptr(aux), _ptr(taps_bar), None,
+                          1 if use_graph else 0), x.device, (self, x, taps, out, aux, taps_bar))
