@@ -51,6 +51,7 @@ __global__ void __launch_bounds__(TB) decimated_kernel(DecArgs a)
     constexpr uint32_t CB = 8, FB = 4;
     static_assert(NP >= 2, "K must take at least two radix passes");
     __shared__ c32 L[K];
+    poison_lds(L, K);
 
     const int tid = threadIdx.x;
     const int M = a.M;

@@ -106,6 +106,21 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Test builds (BT_POISON_LDS defined) fill a kernel's LDS with NaN on entry, so that a
+// read of an element that no thread has written in this launch (a missing store or a
+// barrier in the wrong place) turns the affected outputs into NaN.  No-op otherwise.
+__device__ __forceinline__ void poison_lds(c32 *p, int n)
+{
+#ifdef BT_POISON_LDS
+    const float nan = __builtin_nanf("");
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = c32{nan, nan};
+    __syncthreads();
+#else
+    (void)p;
+    (void)n;
+#endif
+}
+
 // v_r *= w1^r for r = 1..R-1; the powers come from one base root by squaring
 // and single multiplications (at most 2 log2 R products deep)
 template <int R>
@@ -375,6 +390,7 @@ __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
     static_assert(!PAIRL || NBL % 2 == 0, "paired I/O needs an even butterfly count");
 
     __shared__ c32 lds[NP > 1 ? BPW * N : 1];
+    poison_lds(lds, NP > 1 ? BPW * N : 1);
     const int bi = threadIdx.x / TB;
     const int tid = threadIdx.x - bi * TB;
     c32 *L = lds + (NP > 1 ? bi * N : 0);

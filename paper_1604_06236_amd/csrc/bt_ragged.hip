@@ -25,7 +25,13 @@
 
 namespace bt {
 
-constexpr int RT = 1024;  // threads per workgroup of the persistent kernel
+#ifndef BT_RAGGED_RT
+#define BT_RAGGED_RT 1024
+#endif
+#ifndef BT_RAGGED_MIN_WAVES
+#define BT_RAGGED_MIN_WAVES 1
+#endif
+constexpr int RT = BT_RAGGED_RT;  // threads per workgroup of the persistent kernel
 
 struct RaggedItem {
     int cls;              // class index
@@ -49,6 +55,7 @@ struct RaggedArgs {
     int *counter;
     int nitems;
     int div;
+    int lds_elems;            // complex elements of the dynamic LDS (poisoned in test builds)
 };
 
 // Chunk body of one class: `it.count` blocks (plan entries it.first ...) processed as
@@ -342,10 +349,11 @@ static const ClassInfo *class_table(int *count)
 }
 
 template <int SIDE, bool TGR>
-__global__ void __launch_bounds__(RT) ragged_kernel(RaggedArgs a)
+__global__ void __launch_bounds__(RT, BT_RAGGED_MIN_WAVES) ragged_kernel(RaggedArgs a)
 {
     extern __shared__ c32 lds_dyn[];
     __shared__ int item_s;
+    poison_lds(lds_dyn, a.lds_elems);
     for (;;) {
         if (threadIdx.x == 0) item_s = atomicAdd(a.counter, 1);
         __syncthreads();
@@ -589,6 +597,7 @@ static hipError_t ragged_launch(tf_ragged_plan p, int dir, const RaggedArgs &a, 
     hipLaunchKernelGGL(ragged_reset_kernel, dim3(1), dim3(1), 0, s, a.counter + q);
     RaggedArgs av = a;
     av.counter = a.counter + q;
+    av.lds_elems = p->max_lds / int(sizeof(c32));
     if (side == SIDE_IN)
         hipLaunchKernelGGL((ragged_kernel<SIDE_IN, false>), dim3(p->grid[v]), dim3(RT), p->max_lds, s, av);
     else if (tg)
