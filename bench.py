@@ -44,8 +44,8 @@ KERNEL_SOURCES = {
     "ragged": ("bt_ragged.hip", "bt_fused.hpp", "bt_dft.hpp"),
     "fused": ("bt_fused.hpp", "bt_dft.hpp"),
 }
-PROFILE_WORKLOADS = ("ragged", "plain_gpu", "precision", "split_bf16", "split_fp16", "differentiation",
-                     "decimated", "nufft", "schedules", "copy")
+PROFILE_WORKLOADS = ("ragged", "ragged_class", "plain_gpu", "precision", "split_bf16", "split_fp16",
+                     "differentiation", "decimated", "nufft", "schedules", "copy")
 
 
 def kernel_hash(kind: str) -> str:
@@ -605,6 +605,31 @@ def profile_workload(name, reps, T, W):
         torch.cuda.synchronize()
         rb.close()
         print(f"ragged: {reps} x (forward, adjoint, adjoint with tap gradient), 10000 blocks, graph replay",
+              flush=True)
+        return
+    if name == "ragged_class":
+        # one (K, M) class of the ragged batch (BT_CLASS="KxM", default 128x15), about 250 MB
+        # per array with per-block taps: the ragged kernel and then the uniform fused kernel
+        # on the same data, `reps` forward launches each
+        K, M = (int(v) for v in os.environ.get("BT_CLASS", "128x15").split("x"))
+        N = K * M
+        B = int(250e6 // (N * 8))
+        rng = np.random.default_rng(8)
+        S = torch.from_numpy(W.cn01(rng, (B, N)).astype(np.complex64)).to(dev)
+        taps = torch.from_numpy(rng.uniform(0.5, 1.5, (B, N)).astype(np.float32)).to(dev)
+        y = torch.empty_like(S)
+        off = np.arange(B, dtype=np.int64) * N
+        plan = T.RaggedPlan(np.full(B, K), np.full(B, M), off, off, B * N)
+        fr = plan.bind("forward", S.view(-1), taps.view(-1), y.view(-1))
+        for _ in range(reps):
+            fr()
+        torch.cuda.synchronize()
+        ff = T.bind_forward(S, taps, K, M, y)
+        for _ in range(reps):
+            ff()
+        torch.cuda.synchronize()
+        plan.close()
+        print(f"ragged_class: {reps} x ragged forward, then {reps} x fused forward, {B} blocks of ({K}, {M})",
               flush=True)
         return
     if name == "nufft":

@@ -220,16 +220,14 @@ int transform_save_schedule(const char *json_path);
 /* ---------------------------------------------------------------- ragged batches
  * A ragged batch is nblocks blocks with their own (K_b, M_b); block b's
  * points live at complex offset x_off[b] of the flat arrays and its taps at
- * float offset tap_off[b] (per-block taps only).  The plan sorts the blocks
- * by cost into a work list that one persistent kernel drains through an
- * atomic queue.  Supported classes: K_b in {64, 128, 256, 512, 1024} and
- * M_b in {3, 5, 7, 9, 15} (25 compiled classes); any other (K_b, M_b) makes
- * plan creation return TF_EUNSUPPORTED.
- * Concurrency: forward, inverse, adjoint and adjoint with tap gradient each
- * drain their own queue counter, so different directions of one plan may run
- * on different streams at once; two executions of the same direction of one
- * plan must not overlap (they would share one queue): use one plan per stream
- * for that.
+ * float offset tap_off[b] (per-block taps only).  The plan groups the blocks
+ * by class into tiles, cuts them into work items sorted by cost, and one
+ * launch runs one workgroup per item in that order.  Supported classes:
+ * K_b in {64, 128, 256, 512, 1024} and M_b in {3, 5, 7, 9, 15} (25 compiled
+ * classes); any other (K_b, M_b) makes plan creation return TF_EUNSUPPORTED.
+ * Concurrency: a launch keeps no state in the plan's device memory, so
+ * executions of one plan may run on several streams at once.  The plan's HIP
+ * graphs are cached per direction and pointer set under the plan's lock.
  */
 typedef struct tf_ragged_plan_s *tf_ragged_plan;
 
@@ -239,9 +237,9 @@ int transform_ragged_plan_create(const int32_t *K, const int32_t *M, const int64
                                  const int64_t *tap_off, int64_t nblocks, int64_t total_points,
                                  tf_ragged_plan *plan);
 /* The same with an explicit work-item size: each item is `chunk_tiles` tiles
-   (a tile fills one workgroup with blocks of one class); 0 picks about eight
-   items per resident workgroup.  Larger items pipeline better, smaller ones
-   balance better; the autotuner chooses. */
+   (a tile fills one workgroup with blocks of one class); 0 picks four.  Larger
+   items pipeline more tiles through each workgroup, smaller ones balance
+   better; the autotuner chooses. */
 int transform_ragged_plan_create_ex(const int32_t *K, const int32_t *M, const int64_t *x_off,
                                     const int64_t *tap_off, int64_t nblocks, int64_t total_points,
                                     int32_t chunk_tiles, tf_ragged_plan *plan);

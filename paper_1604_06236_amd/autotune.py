@@ -76,7 +76,7 @@ def tune_shape(T, K, M, B, caps=(0, 256, 512, 1024, 2048), reps=50, nbuf=4, verb
     return best, results
 
 
-def tune_ragged(T, W, chunks=(0, 1, 2, 4, 8, 16), reps=10, verbose=True):
+def tune_ragged(T, W, chunks=(1, 2, 3, 4, 6, 8), reps=10, verbose=True):
     """Time forward + adjoint of the standard ragged batch for several work-item
     sizes (tiles per item); returns the best size."""
     import numpy as np

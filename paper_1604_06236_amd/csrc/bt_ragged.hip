@@ -1,15 +1,16 @@
-// Ragged batches: blocks of different (K, M) in one persistent launch.
+// Ragged batches: blocks of different (K, M) in one launch.
 //
 // Every block is an independent instance of the transform of eq. (6) on its
 // own grid (its own N = K M, filter and offset).  The plan groups blocks of
-// one (K, M) class into tiles (as many blocks as fill a workgroup), sorts the
-// tiles by cost (N log2 N per block, largest first) and lays them out as work
-// items.  One persistent kernel, sized to the resident capacity of the GPU,
-// drains the items through an atomic counter; each item runs the class's
-// compiled tile body (radix plan, threads per block, blocks per tile) with
-// the same pass machinery as the uniform kernel.  The counter is cleared by a
-// one-thread kernel launched just before, so the pair can be captured in a
-// HIP graph and replayed.
+// one (K, M) class into tiles (as many blocks as fill a workgroup), cuts them
+// into work items of a few same-class tiles and sorts the items by cost
+// (N log2 N per block, largest first).  One launch runs one workgroup per
+// item: the hardware dispatcher hands the items out in cost order as
+// workgroups retire, so there is no queue in memory and the launch replays
+// from a HIP graph as it is.  Each item runs its class's compiled tile body
+// (radix plan, threads per block, blocks per tile) with the same pass
+// machinery as the uniform kernel; within an item the next tile's inputs are
+// fetched while the current tile runs its LDS passes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -52,8 +53,6 @@ struct RaggedArgs {
     const RaggedItem *items;
     const c32 *tw;            // concatenated base-root tables of the classes
     const int *tw_off;        // per class
-    int *counter;
-    int nitems;
     int div;
     int lds_elems;            // complex elements of the dynamic LDS (poisoned in test builds)
 };
@@ -348,32 +347,23 @@ static const ClassInfo *class_table(int *count)
     return t.data();
 }
 
+// one workgroup per work item
 template <int SIDE, bool TGR>
 __global__ void __launch_bounds__(RT, BT_RAGGED_MIN_WAVES) ragged_kernel(RaggedArgs a)
 {
     extern __shared__ c32 lds_dyn[];
-    __shared__ int item_s;
     poison_lds(lds_dyn, a.lds_elems);
-    for (;;) {
-        if (threadIdx.x == 0) item_s = atomicAdd(a.counter, 1);
-        __syncthreads();
-        const int item = item_s;
-        __syncthreads();
-        if (item >= a.nitems) break;     // every workgroup reaches this once the queue is empty
-        const RaggedItem it = a.items[item];
-        int cls = 0;
+    const RaggedItem it = a.items[blockIdx.x];
+    int cls = 0;
 #define BT_CLASS_CASE(K_, M_)                                                                      \
     if (it.cls == cls) {                                                                           \
         using C = RClass<K_, M_>;                                                                  \
-        ragged_chunk<typename C::PL, C::TB, C::BPW, SIDE, TGR, C::template pf<SIDE, TGR>()>(a, it, lds_dyn);           \
+        ragged_chunk<typename C::PL, C::TB, C::BPW, SIDE, TGR, C::template pf<SIDE, TGR>()>(a, it, lds_dyn); \
     }                                                                                              \
     ++cls;
-        BT_RAGGED_CLASSES(BT_CLASS_CASE)
+    BT_RAGGED_CLASSES(BT_CLASS_CASE)
 #undef BT_CLASS_CASE
-    }
 }
-
-__global__ void ragged_reset_kernel(int *counter) { *counter = 0; }
 
 // ------------------------------------------------------------------ plan
 struct GraphKey {
@@ -393,12 +383,10 @@ struct tf_ragged_plan_s {
     int64_t nblocks = 0;
     int nitems = 0;
     int max_lds = 0;
-    int grid[3] = {0, 0, 0};
     int64_t *x_off = nullptr, *tap_off = nullptr;   // in plan order
     bt::RaggedItem *items = nullptr;
     bt::c32 *tw = nullptr;
     int *tw_off = nullptr;
-    int *counter = nullptr;
     hipStream_t capture_stream = nullptr;
     std::map<bt::GraphKey, hipGraphExec_t> graphs;
     std::mutex mu;
@@ -421,7 +409,6 @@ static void plan_free(tf_ragged_plan p)
     (void)hipFree(p->items);
     (void)hipFree(p->tw);
     (void)hipFree(p->tw_off);
-    (void)hipFree(p->counter);
     if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
     delete p;
 }
@@ -477,23 +464,13 @@ extern "C" int transform_ragged_plan_create_ex(const int32_t *K, const int32_t *
         if (x_off[b] < 0 || x_off[b] + N > total_points || tap_off[b] < 0) return TF_EINVAL;
         members[f->second].push_back(int(b));
     }
-    // chunks of `chunk_tiles` tiles of same-class blocks, sorted by cost (largest
-    // first); 0 picks about eight chunks per resident workgroup
-    int64_t tiles = 0;
+    // work items of `chunk_tiles` tiles of same-class blocks, sorted by cost (largest
+    // first); 0 picks four (each tile after the first has its inputs fetched while the
+    // previous one runs)
     int max_lds = 0;
-    for (int c = 0; c < ncls; ++c) {
-        if (members[c].empty()) continue;
-        tiles += (int64_t(members[c].size()) + cls[c].BPW - 1) / cls[c].BPW;
-        max_lds = std::max(max_lds, cls[c].lds);
-    }
-    int dev_cus = 0;
-    {
-        int d = 0;
-        if (hipGetDevice(&d) != hipSuccess ||
-            hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, d) != hipSuccess)
-            dev_cus = 256;
-    }
-    if (chunk_tiles == 0) chunk_tiles = int(std::max<int64_t>(1, tiles / (8 * int64_t(dev_cus))));
+    for (int c = 0; c < ncls; ++c)
+        if (!members[c].empty()) max_lds = std::max(max_lds, cls[c].lds);
+    if (chunk_tiles == 0) chunk_tiles = 4;
     std::vector<int> order;
     std::vector<RaggedItem> items;
     std::vector<double> cost;
@@ -552,23 +529,13 @@ extern "C" int transform_ragged_plan_create_ex(const int32_t *K, const int32_t *
     if (!rc) rc = upload_vec(sorted, &p->items);
     if (!rc) rc = upload_vec(tw, &p->tw);
     if (!rc) rc = upload_vec(tw_off, &p->tw_off);
-    if (!rc) rc = upload_vec(std::vector<int>{0, 0, 0, 0}, &p->counter);   // one queue per direction
-    // persistent grid: the resident capacity for this LDS size, per kernel variant
-    int cus = 0;
-    if (!rc && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess)
-        rc = TF_EHIP;
+
     for (int v = 0; v < 3 && !rc; ++v) {
         const void *k = ragged_kernel_ptr(v == 0 ? SIDE_IN : SIDE_OUT, v == 2);
         if (max_lds > 64 * 1024) {
             hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
             if (e != hipSuccess) rc = fail("hipFuncSetAttribute", e);
         }
-        int occ = 0;
-        if (!rc) {
-            hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, RT, max_lds);
-            if (e != hipSuccess) rc = fail("occupancy", e);
-        }
-        p->grid[v] = std::max(1, std::min(occ * cus, std::max(p->nitems, 1)));
     }
     if (!rc) {
         hipError_t e = hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking);
@@ -592,18 +559,15 @@ static hipError_t ragged_launch(tf_ragged_plan p, int dir, const RaggedArgs &a, 
 {
     const int side = dir == 0 ? SIDE_IN : SIDE_OUT;
     const bool tg = a.tapbar != nullptr;
-    const int v = dir == 0 ? 0 : (tg ? 2 : 1);
-    const int q = dir + (tg ? 1 : 0);     // forward, inverse, adjoint, adjoint with tap gradient
-    hipLaunchKernelGGL(ragged_reset_kernel, dim3(1), dim3(1), 0, s, a.counter + q);
     RaggedArgs av = a;
-    av.counter = a.counter + q;
     av.lds_elems = p->max_lds / int(sizeof(c32));
+    const dim3 grid(p->nitems);
     if (side == SIDE_IN)
-        hipLaunchKernelGGL((ragged_kernel<SIDE_IN, false>), dim3(p->grid[v]), dim3(RT), p->max_lds, s, av);
+        hipLaunchKernelGGL((ragged_kernel<SIDE_IN, false>), grid, dim3(RT), p->max_lds, s, av);
     else if (tg)
-        hipLaunchKernelGGL((ragged_kernel<SIDE_OUT, true>), dim3(p->grid[v]), dim3(RT), p->max_lds, s, av);
+        hipLaunchKernelGGL((ragged_kernel<SIDE_OUT, true>), grid, dim3(RT), p->max_lds, s, av);
     else
-        hipLaunchKernelGGL((ragged_kernel<SIDE_OUT, false>), dim3(p->grid[v]), dim3(RT), p->max_lds, s, av);
+        hipLaunchKernelGGL((ragged_kernel<SIDE_OUT, false>), grid, dim3(RT), p->max_lds, s, av);
     return hipGetLastError();
 }
 
@@ -633,8 +597,6 @@ extern "C" int transform_ragged_execute(tf_ragged_plan plan, int32_t direction, 
     a.items = plan->items;
     a.tw = plan->tw;
     a.tw_off = plan->tw_off;
-    a.counter = plan->counter;
-    a.nitems = plan->nitems;
     a.div = direction == 1;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     std::lock_guard<std::mutex> lk(plan->mu);
