@@ -582,10 +582,10 @@ extern "C" int transform_schedule_describe(int32_t K, int32_t M, int32_t idx, ch
     std::snprintf(buf, buflen,
                   "{\"K\": %d, \"M\": %d, \"radices\": [%s], \"threads_per_block\": %d, "
                   "\"blocks_per_workgroup\": %d, \"lds_bytes\": %d, \"prefetch\": %s, "
-                  "\"sequential_twiddles\": %s, \"paired_io\": %s, \"nontemporal\": %s}",
+                  "\"sequential_twiddles\": %s, \"paired_io\": %s, \"nontemporal\": %s, \"early_fetch\": %s}",
                   e.K, e.M, rad.c_str(), e.TB, e.BPW, e.lds_bytes, (e.opt & OPT_NO_PREFETCH) ? "false" : "true",
                   (e.opt & OPT_SEQ_TWIDDLE) ? "true" : "false", (e.opt & OPT_PAIRED_IO) ? "true" : "false",
-                  (e.opt & OPT_NT) ? "true" : "false");
+                  (e.opt & OPT_NT) ? "true" : "false", (e.opt & OPT_EARLY_FETCH) ? "true" : "false");
     return TF_OK;
 }
 

@@ -167,6 +167,7 @@ enum : int {
     OPT_SEQ_TWIDDLE = 2,   // sequential twiddle powers
     OPT_PAIRED_IO = 4,     // first/last pass: a thread owns two adjacent butterflies (16-byte I/O)
     OPT_NT = 8,            // non-temporal hint on the streaming HBM loads and stores
+    OPT_EARLY_FETCH = 16,  // prefetch each pass-0 row of the next group as soon as its DFT is done
 };
 
 template <int OPT, int R>
@@ -437,44 +438,40 @@ __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
     // pass-0 operands of the group being processed: raw input and input-side taps
     c32 x0[IT0][R0];
     float t0[SIDE == SIDE_IN ? IT0 : 1][SIDE == SIDE_IN ? R0 : 1];
-    auto fetch = [&](int64_t g) {
+    // row i of group g (with paired I/O: rows i and i + 1, i even)
+    auto fetch_row = [&](int64_t g, int i) {
         const rsrc_t ri = rs_cplx(a.in, g);
         const rsrc_t rt = rs_taps(g);
         const uint32_t tb = shared_taps ? 0u : boff;
-        if constexpr (PAIR0) {
-#pragma unroll
-            for (int i = 0; i < IT0; i += 2) {
-                const int j = MP::template j<0>(tid, i);
-                if (FULL0 || j < NB0) {
-                    static_for<0, R0>([&](auto rI) {
-                        constexpr int r = decltype(rI)::value;
-                        const c32x2 p = ld_c2<NTA>(ri, (boff + j) * CB, r * NB0 * CB);
-                        x0[i][r] = p.a;
-                        x0[i + 1][r] = p.b;
-                        if constexpr (SIDE == SIDE_IN) {
-                            const f32x2 t = ld_f2(rt, (tb + j) * FB, r * NB0 * FB);
-                            t0[i][r] = t.a;
-                            t0[i + 1][r] = t.b;
-                        }
-                    });
+        const int j = MP::template j<0>(tid, i);
+        if (FULL0 || j < NB0) {
+            static_for<0, R0>([&](auto rI) {
+                constexpr int r = decltype(rI)::value;
+                if constexpr (PAIR0) {
+                    const c32x2 p = ld_c2<NTA>(ri, (boff + j) * CB, r * NB0 * CB);
+                    x0[i][r] = p.a;
+                    x0[i + 1][r] = p.b;
+                    if constexpr (SIDE == SIDE_IN) {
+                        const f32x2 t = ld_f2(rt, (tb + j) * FB, r * NB0 * FB);
+                        t0[i][r] = t.a;
+                        t0[i + 1][r] = t.b;
+                    }
+                } else {
+                    x0[i][r] = ld_c<NTA>(ri, (boff + j) * CB, r * NB0 * CB);
+                    if constexpr (SIDE == SIDE_IN) t0[i][r] = ld_f(rt, (tb + j) * FB, r * NB0 * FB);
                 }
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < IT0; ++i) {
-                const int j = MP::template j<0>(tid, i);
-                if (FULL0 || j < NB0) {
-                    static_for<0, R0>([&](auto rI) {
-                        constexpr int r = decltype(rI)::value;
-                        x0[i][r] = ld_c<NTA>(ri, (boff + j) * CB, r * NB0 * CB);
-                        if constexpr (SIDE == SIDE_IN) t0[i][r] = ld_f(rt, (tb + j) * FB, r * NB0 * FB);
-                    });
-                }
-            }
+            });
         }
+    };
+    auto fetch = [&](int64_t g) {
+#pragma unroll
+        for (int i = 0; i < IT0; i += PAIR0 ? 2 : 1) fetch_row(g, i);
     };
 
     constexpr bool PREFETCH = !(OPT & OPT_NO_PREFETCH);
+    // early: row i of the next group is requested right after row i's pass-0 DFT (its registers
+    // are free from then on), so the CU has loads in flight during the rest of pass 0
+    constexpr bool EARLY = PREFETCH && (OPT & OPT_EARLY_FETCH) && NP > 1;
     int64_t g = blockIdx.x;
     if (PREFETCH && g < ngroups) fetch(g);
     for (; g < ngroups; g += gridDim.x) {
@@ -559,6 +556,9 @@ __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
                     });
                     dft<R0>(v0[i]);
                 }
+                if constexpr (EARLY) {
+                    if (g + gridDim.x < ngroups && (!PAIR0 || (i & 1))) fetch_row(g + gridDim.x, PAIR0 ? i - 1 : i);
+                }
             }
             lds_barrier();   // the previous group's last pass has finished reading LDS
 #pragma unroll
@@ -573,7 +573,7 @@ __global__ void __launch_bounds__(TB *BPW) fused_kernel(FusedArgs a)
             }
             // ---- start reading the next group while this one runs in LDS, and the
             //      operands the last pass needs (output-side taps, S for the tap term)
-            if (PREFETCH && g + gridDim.x < ngroups) fetch(g + gridDim.x);
+            if (PREFETCH && !EARLY && g + gridDim.x < ngroups) fetch(g + gridDim.x);
             float tl[SIDE == SIDE_OUT ? ITL : 1][SIDE == SIDE_OUT ? RL : 1];
             c32 sl[TG == TG_OUT_ ? ITL : 1][TG == TG_OUT_ ? RL : 1];
 #pragma unroll

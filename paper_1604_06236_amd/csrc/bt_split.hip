@@ -66,7 +66,8 @@ struct PrecFP16 {
     __device__ static f4 mma32(V8 a, V8 b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
 };
 
-// split of a complex vector into hi/lo parts of re, im and -im
+// split of a complex vector into hi/lo parts of re and im; the constant operands (the DFT
+// matrices) also carry -im, so that the data operands never need a negated copy
 template <class P, int W>
 struct SplitC {
     typedef typename P::T T;
@@ -84,21 +85,27 @@ struct SplitC {
     }
 };
 
-// complex tile product D += A B, A and B split; each real product with 3 MFMAs
-template <class P, int W>
+template <class P, int W, class V>
+__device__ __forceinline__ f4 mma(V a, V b, f4 c)
+{
+    if constexpr (W == 4) return P::mma16(a, b, c);
+    else return P::mma32(a, b, c);
+}
+
+// complex tile product D += A B, A and B split; each real product with 3 MFMAs (the lo*lo term
+// dropped).  NEG_A: the -Im(A) Im(B) term takes A's negated parts (A constant), else B's (B
+// constant).
+template <class P, int W, bool NEG_A>
 __device__ __forceinline__ void cmma(const SplitC<P, W> &A, const SplitC<P, W> &B, f4 &dr, f4 &di)
 {
-    if constexpr (W == 4) {
-        dr = P::mma16(A.rh, B.rh, dr); dr = P::mma16(A.rh, B.rl, dr); dr = P::mma16(A.rl, B.rh, dr);
-        dr = P::mma16(A.ih, B.nih, dr); dr = P::mma16(A.ih, B.nil, dr); dr = P::mma16(A.il, B.nih, dr);
-        di = P::mma16(A.rh, B.ih, di); di = P::mma16(A.rh, B.il, di); di = P::mma16(A.rl, B.ih, di);
-        di = P::mma16(A.ih, B.rh, di); di = P::mma16(A.ih, B.rl, di); di = P::mma16(A.il, B.rh, di);
+    dr = mma<P, W>(A.rh, B.rh, dr); dr = mma<P, W>(A.rh, B.rl, dr); dr = mma<P, W>(A.rl, B.rh, dr);
+    if constexpr (NEG_A) {
+        dr = mma<P, W>(A.nih, B.ih, dr); dr = mma<P, W>(A.nih, B.il, dr); dr = mma<P, W>(A.nil, B.ih, dr);
     } else {
-        dr = P::mma32(A.rh, B.rh, dr); dr = P::mma32(A.rh, B.rl, dr); dr = P::mma32(A.rl, B.rh, dr);
-        dr = P::mma32(A.ih, B.nih, dr); dr = P::mma32(A.ih, B.nil, dr); dr = P::mma32(A.il, B.nih, dr);
-        di = P::mma32(A.rh, B.ih, di); di = P::mma32(A.rh, B.il, di); di = P::mma32(A.rl, B.ih, di);
-        di = P::mma32(A.ih, B.rh, di); di = P::mma32(A.ih, B.rl, di); di = P::mma32(A.il, B.rh, di);
+        dr = mma<P, W>(A.ih, B.nih, dr); dr = mma<P, W>(A.ih, B.nil, dr); dr = mma<P, W>(A.il, B.nih, dr);
     }
+    di = mma<P, W>(A.rh, B.ih, di); di = mma<P, W>(A.rh, B.il, di); di = mma<P, W>(A.rl, B.ih, di);
+    di = mma<P, W>(A.ih, B.rh, di); di = mma<P, W>(A.ih, B.rl, di); di = mma<P, W>(A.il, B.rh, di);
 }
 
 struct SplitArgs {
@@ -175,26 +182,29 @@ __global__ void __launch_bounds__(ST) split_kernel(SplitArgs a)
     float tin[SIDE == SIDE_IN ? TPW : 1][SIDE == SIDE_IN ? 4 : 1];
     // every call overwrites all of xin / tin (zeros past the batch), so that they
     // are dead between stage A and the next fetch
+    // buffer resources over exactly the block's N points: rows r >= M (n >= N) and blocks past
+    // the batch (range 0) read as zero
     auto fetch = [&](int64_t bb) {
         const bool valid = bb < a.nblocks;
         const int64_t bc = valid ? bb : 0;
-        const c32 *inb = a.in + bc * N;
-        const float *tpb = a.taps + bc * a.tap_stride;
+        const rsrc_t ri = make_rsrc(a.in + bc * N, valid ? uint32_t(N) * 8u : 0u);
+        const rsrc_t rt = make_rsrc(a.taps + bc * a.tap_stride, valid ? uint32_t(N) * 4u : 0u);
 #pragma unroll
-        for (int i = 0; i < TPW; ++i)
+        for (int i = 0; i < TPW; ++i) {
+            const uint32_t n0 = 16 * (w + i * (ST / 64)) + c + K * 4 * g;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int r = 4 * g + j;
-                const int n = 16 * (w + i * (ST / 64)) + c + K * r;
-                xin[i][j] = (valid && r < M) ? inb[n] : c32{0.f, 0.f};
-                if constexpr (SIDE == SIDE_IN) tin[i][j] = (valid && r < M) ? tpb[n] : 0.f;
+                xin[i][j] = ld_c(ri, n0 * 8u, uint32_t(K * j) * 8u);
+                if constexpr (SIDE == SIDE_IN) tin[i][j] = ld_f(rt, n0 * 4u, uint32_t(K * j) * 4u);
             }
+        }
     };
+
 
     fetch(blockIdx.x);
     for (int64_t b = blockIdx.x; b < a.nblocks; b += gridDim.x) {
-        c32 *outb = a.out + b * N;
-        const float *tp = a.taps + b * a.tap_stride;
+        const rsrc_t rso = make_rsrc(a.out + b * N, uint32_t(N) * 8u);
+        const rsrc_t rst = make_rsrc(a.taps + b * a.tap_stride, uint32_t(N) * 4u);
 
         // ---- stage A: per 16-column tile of p, U = F_M Z, then the coset twiddle
         float sZ = 1.0f;
@@ -229,7 +239,7 @@ __global__ void __launch_bounds__(ST) split_kernel(SplitArgs a)
                 z.set(j, scale(x, sZ));
             }
             f4 dr = {0.f, 0.f, 0.f, 0.f}, di = {0.f, 0.f, 0.f, 0.f};
-            cmma<P, 4>(fm, z, dr, di);
+            cmma<P, 4, false>(fm, z, dr, di);
             const int p = 16 * t + c;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -266,7 +276,7 @@ __global__ void __launch_bounds__(ST) split_kernel(SplitArgs a)
                 for (int tq2 = 0; tq2 < NKT; ++tq2) {
                     vr[tp1][tq2] = f4{0.f, 0.f, 0.f, 0.f};
                     vi[tp1][tq2] = f4{0.f, 0.f, 0.f, 0.f};
-                    cmma<P, KW>(A, fk[tq2], vr[tp1][tq2], vi[tp1][tq2]);
+                    cmma<P, KW, false>(A, fk[tq2], vr[tp1][tq2], vi[tp1][tq2]);
                 }
             }
             // twiddle e^{+j 2 pi p1 q2 / K}; lane holds p1 = 16 tp1 + 4g + j, q2 = 16 tq2 + c
@@ -298,7 +308,7 @@ __global__ void __launch_bounds__(ST) split_kernel(SplitArgs a)
 #pragma unroll
                 for (int tq1 = 0; tq1 < NKT; ++tq1) {
                     f4 xr = {0.f, 0.f, 0.f, 0.f}, xi = {0.f, 0.f, 0.f, 0.f};
-                    cmma<P, KW>(fk[tq1], B, xr, xi);   // F_KS is symmetric: A layout of tile tq1
+                    cmma<P, KW, true>(fk[tq1], B, xr, xi);   // F_KS is symmetric: A layout of tile tq1
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const int q1 = 16 * tq1 + 4 * g + j, q2 = 16 * tq2 + c;
@@ -319,7 +329,7 @@ __global__ void __launch_bounds__(ST) split_kernel(SplitArgs a)
             float tv[8];
             if constexpr (SIDE == SIDE_OUT) {
 #pragma unroll
-                for (int k = 0; k < 8; ++k) tv[k] = u0 + k * ST < N ? tp[u0 + k * ST] : 0.f;
+                for (int k = 0; k < 8; ++k) tv[k] = ld_f(rst, uint32_t(u0) * 4u, uint32_t(k * ST) * 4u);
             }
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
@@ -328,7 +338,7 @@ __global__ void __launch_bounds__(ST) split_kernel(SplitArgs a)
                     c32 y = U[m * RS + q];
                     if (conj_io) y = conj(y);
                     if constexpr (SIDE == SIDE_OUT) y = scale(y, tv[k]);
-                    outb[u] = y;
+                    st_c(y, rso, uint32_t(u) * 8u, 0u);
                 }
                 q += dq;
                 m += dm;
