@@ -326,17 +326,22 @@ static int run(const void *in, const float *taps, void *out, const void *aux, fl
     const int64_t N = int64_t(K) * M;
     const bool shared = tap_stride == 0;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    std::lock_guard<std::mutex> lk(g_mu);
     int dev = 0;
     int rc = current_device(&dev);
     if (rc) return rc;
+    // The lock covers the lookups in the shared caches only (schedule choice, per-device
+    // tables, occupancies); what they hand out lives until the process ends, so the launches
+    // themselves run unlocked and calls from several threads or streams do not serialise.
 
     if (compute == TF_PLAIN_FP32) {
         if (tg && side == SIDE_IN) return TF_EUNSUPPORTED;
         const size_t need = plain_ws_bytes(nblocks, N, tg, shared);
         if (!ws || ws_bytes < need || !aligned(ws, 8)) return TF_EWORKSPACE;
         const c32 *roots = nullptr;
-        rc = plain_roots(dev, K, M, &roots);
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            rc = plain_roots(dev, K, M, &roots);
+        }
         if (rc) return rc;
         c32 *ws0 = reinterpret_cast<c32 *>(ws);
         c32 *ws1 = ws0 + nblocks * N;
@@ -368,7 +373,10 @@ static int run(const void *in, const float *taps, void *out, const void *aux, fl
 
     Geometry g{};
     const c32 *tw = nullptr;
-    rc = fused_geometry(dev, K, M, nblocks, side, tg, tg && shared, &g, &tw, ws_caps_grid ? ws_bytes : 0);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        rc = fused_geometry(dev, K, M, nblocks, side, tg, tg && shared, &g, &tw, ws_caps_grid ? ws_bytes : 0);
+    }
     if (rc) return rc;
     float *part = nullptr;
     if (tg && shared) {
