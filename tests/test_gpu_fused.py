@@ -367,3 +367,43 @@ def test_standard_config_full_size(T, cfg):
                                    want_taps_bar=True)
     expect = K * M * taps.astype(np.float64) * np.sum(np.abs(S.astype(np.complex128)) ** 2, axis=0)
     assert rel_l2(_host(tb_fs), expect) < TOL
+
+
+def test_concurrent_calls_from_threads(T):
+    """Calls from several host threads, each on its own stream, interleave their launches (the
+    library locks only its cache lookups): every call's output meets the bar, forward and
+    adjoint with the shared tap gradient (whose partial rows live in per-call workspaces)."""
+    import threading
+    import torch
+    K, M, B = 128, 15, 48
+    S, taps = _inputs(B, K, M, seed=21)
+    y = W.cn01(np.random.default_rng(22), (B, K * M)).astype(np.complex64)
+    y_ref = O.forward(S, taps)
+    sb_ref, tb_ref = O.adjoint(y, taps, S)
+    dS, dt, dy = _dev(S), _dev(taps), _dev(y)
+    results, errors = {}, []
+
+    def worker(k):
+        try:
+            st = torch.cuda.Stream()
+            outs = []
+            with torch.cuda.stream(st):
+                for _ in range(20):
+                    outs.append(T.transform_forward(dS, dt, K, M))
+                    outs.append(T.transform_adjoint(dy, dt, K, M, coeffs=dS, want_taps_bar=True))
+            st.synchronize()
+            results[k] = outs
+        except Exception as e:  # reported below
+            errors.append(repr(e))
+
+    threads = [threading.Thread(target=worker, args=(k,)) for k in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    assert not errors, errors
+    for k, outs in results.items():
+        for i in range(0, len(outs), 2):
+            assert rel_l2(_host(outs[i]), y_ref) < TOL, (k, i)
+            sb, tb = outs[i + 1]
+            assert rel_l2(_host(sb), sb_ref) < TOL and rel_l2(_host(tb), tb_ref) < TOL, (k, i)
