@@ -57,6 +57,13 @@ struct RaggedArgs {
     int lds_elems;            // complex elements of the dynamic LDS (poisoned in test builds)
 };
 
+__device__ __forceinline__ int64_t uniform64(int64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(v));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v) >> 32));
+    return int64_t((uint64_t(hi) << 32) | lo);
+}
+
 // Chunk body of one class: `it.count` blocks (plan entries it.first ...) processed as
 // tiles of up to BPW blocks, TB threads per block (TB >= 64, so a wave never
 // straddles two blocks and block bases are wave-uniform).  With PF the next
@@ -116,12 +123,17 @@ __device__ __forceinline__ void ragged_chunk(const RaggedArgs &a, const RaggedIt
     };
     auto res = [&](int t) {
         Res r;
-        const int slot = t * BPW + bi;
+        // the slot is wave-uniform (a wave never straddles two blocks); taking it through
+        // readfirstlane makes the validity and the resource range scalar too, so the buffer
+        // instructions get their descriptors from SGPRs as they are (a per-lane range would
+        // wrap every buffer access in a loop over the distinct descriptors of the wave)
+        const int slot = __builtin_amdgcn_readfirstlane(t * BPW + bi);
         r.valid = slot < it.count;
-        int e = r.valid ? it.first + slot : 0;
-        e = __builtin_amdgcn_readfirstlane(e);
-        const int64_t xo = a.x_off[e];
-        const int64_t to = a.tap_off[e];
+        const int e = r.valid ? it.first + slot : 0;
+        // the offsets are wave-uniform; the compiler may still load them into VGPRs (a vector
+        // load it cannot prove unclobbered), so they are made scalar explicitly
+        const int64_t xo = uniform64(a.x_off[e]);
+        const int64_t to = uniform64(a.tap_off[e]);
         const uint32_t nb = r.valid ? N : 0;
         r.in = make_rsrc(a.in + xo, nb * CB);
         r.out = make_rsrc(a.out + xo, nb * CB);
@@ -323,6 +335,17 @@ struct RClass {
     X(512, 15) X(1024, 3) X(1024, 5) X(1024, 7) X(1024, 9) X(1024, 15)
 #endif
 
+// position of (K, M) in the class list (the plan's class index)
+#define BT_CLASS_KM(K_, M_) K_ * 64 + M_,
+constexpr int kClassKM[] = {BT_RAGGED_CLASSES(BT_CLASS_KM)};
+#undef BT_CLASS_KM
+constexpr int class_index(int K, int M)
+{
+    for (int i = 0; i < int(sizeof(kClassKM) / sizeof(kClassKM[0])); ++i)
+        if (kClassKM[i] == K * 64 + M) return i;
+    return -1;
+}
+
 struct ClassInfo {
     int K, M, N, TB, BPW, lds, npass;
     int radix[8];
@@ -354,15 +377,20 @@ __global__ void __launch_bounds__(RT, BT_RAGGED_MIN_WAVES) ragged_kernel(RaggedA
     extern __shared__ c32 lds_dyn[];
     poison_lds(lds_dyn, a.lds_elems);
     const RaggedItem it = a.items[blockIdx.x];
-    int cls = 0;
+    // one switch (a scalar compare tree) rather than a chain of tests whose merges the
+    // compiler carries as predicate masks through every class
+    switch (it.cls) {
 #define BT_CLASS_CASE(K_, M_)                                                                      \
-    if (it.cls == cls) {                                                                           \
+    case class_index(K_, M_): {                                                                    \
         using C = RClass<K_, M_>;                                                                  \
         ragged_chunk<typename C::PL, C::TB, C::BPW, SIDE, TGR, C::template pf<SIDE, TGR>()>(a, it, lds_dyn); \
-    }                                                                                              \
-    ++cls;
-    BT_RAGGED_CLASSES(BT_CLASS_CASE)
+        break;                                                                                     \
+    }
+        BT_RAGGED_CLASSES(BT_CLASS_CASE)
 #undef BT_CLASS_CASE
+    default:
+        break;
+    }
 }
 
 // ------------------------------------------------------------------ plan
