@@ -283,10 +283,11 @@ template <> struct RKPlan<1024> { using type = Radices<8, 8, 16>; };
 // CEIL rounds the threads per block up to the next power of two above the
 // widest pass (fewer elements per thread); the PF_* flags say whether the
 // forward / tap-gradient adjoint / plain adjoint prefetch the next tile (a
-// second copy of the pass-0 operands in registers).  The defaults fit most
-// classes; the specialisations below are the classes whose compiled code
-// otherwise spills (values read from the compiler's per-kernel VGPR and spill
-// counts).
+// second copy of the pass-0 operands in registers).  Every forward and plain
+// adjoint body fits with the prefetch; the specialisations below keep CEIL
+// where it was measured to help and drop the prefetch from the tap-gradient
+// bodies that would otherwise spill (per-class VGPR and spill counts of the
+// compiler, one class compiled at a time).
 template <int K, int M> struct RTune {
     static constexpr bool CEIL = false;
     static constexpr bool PF_FWD = true, PF_TG = true, PF_ADJ = true;
@@ -298,19 +299,12 @@ template <int K, int M> struct RTune {
     };
 BT_RTUNE(64, 9, true, true, true, true)
 BT_RTUNE(64, 15, false, true, false, true)
-BT_RTUNE(128, 9, false, true, false, true)
 BT_RTUNE(128, 15, false, true, false, true)
-BT_RTUNE(256, 3, false, true, false, true)
-BT_RTUNE(256, 5, false, true, false, true)
-BT_RTUNE(256, 7, false, true, false, true)
-BT_RTUNE(256, 9, false, true, false, true)
 BT_RTUNE(256, 15, false, true, false, true)
 BT_RTUNE(512, 9, true, true, true, true)
-BT_RTUNE(512, 15, true, true, false, true)
-BT_RTUNE(1024, 5, false, true, false, true)
-BT_RTUNE(1024, 7, false, true, false, true)
+BT_RTUNE(512, 15, true, true, true, true)
 BT_RTUNE(1024, 9, false, true, false, true)
-BT_RTUNE(1024, 15, false, true, false, false)
+BT_RTUNE(1024, 15, false, true, false, true)
 #undef BT_RTUNE
 
 template <int K, int M>
