@@ -28,6 +28,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/blocktransform.h"
@@ -173,9 +174,9 @@ __global__ void __launch_bounds__(ST) split_kernel(SplitArgs a)
         }
 
     // stage-A operands of one block in registers (each wave owns TPW column tiles),
-    // with the input-side taps.  The next block's are fetched after the B stages, so
-    // that they are in flight during the write-out (held across the B stages they
-    // would spill the 32-point stages)
+    // with the input-side taps.  The next block's are fetched before and after the B
+    // stages (EARLY tiles before), so that they are in flight during the B stages and the
+    // write-out (all of them held across the B stages would spill the 32-point stages)
     constexpr int TPW = NT / (ST / 64);
     static_assert(NT % (ST / 64) == 0, "stage-A tiles must divide among the waves");
     c32 xin[TPW][4];
@@ -184,13 +185,14 @@ __global__ void __launch_bounds__(ST) split_kernel(SplitArgs a)
     // are dead between stage A and the next fetch
     // buffer resources over exactly the block's N points: rows r >= M (n >= N) and blocks past
     // the batch (range 0) read as zero
-    auto fetch = [&](int64_t bb) {
+    auto fetch_range = [&](int64_t bb, auto i0c, auto i1c) {
+        constexpr int I0 = decltype(i0c)::value, I1 = decltype(i1c)::value;
         const bool valid = bb < a.nblocks;
         const int64_t bc = valid ? bb : 0;
         const rsrc_t ri = make_rsrc(a.in + bc * N, valid ? uint32_t(N) * 8u : 0u);
         const rsrc_t rt = make_rsrc(a.taps + bc * a.tap_stride, valid ? uint32_t(N) * 4u : 0u);
 #pragma unroll
-        for (int i = 0; i < TPW; ++i) {
+        for (int i = I0; i < I1; ++i) {
             const uint32_t n0 = 16 * (w + i * (ST / 64)) + c + K * 4 * g;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -198,6 +200,13 @@ __global__ void __launch_bounds__(ST) split_kernel(SplitArgs a)
                 if constexpr (SIDE == SIDE_IN) tin[i][j] = ld_f(rt, n0 * 4u, uint32_t(K * j) * 4u);
             }
         }
+    };
+    // tiles of the next block requested before the B stages (the rest after them): as many as
+    // fit beside the B stages' registers without spilling (measured: BF16 at K = 1024 gains
+    // 2-3 % with two, FP16 spills with any)
+    constexpr int EARLY = KS == 16 ? TPW : (P::scaled ? 0 : 2);
+    auto fetch = [&](int64_t bb) {
+        fetch_range(bb, std::integral_constant<int, 0>{}, std::integral_constant<int, TPW>{});
     };
 
 
@@ -261,6 +270,8 @@ __global__ void __launch_bounds__(ST) split_kernel(SplitArgs a)
             sU = pow2_scale(mx);
         }
 
+        if constexpr (EARLY > 0)
+            fetch_range(b + gridDim.x, std::integral_constant<int, 0>{}, std::integral_constant<int, EARLY>{});
         // ---- stages B1, B2: one row m per wave
         for (int m = w; m < M; m += ST / 64) {
             f4 vr[NKT][NKT], vi[NKT][NKT];
@@ -318,7 +329,7 @@ __global__ void __launch_bounds__(ST) split_kernel(SplitArgs a)
             }
         }
         __syncthreads();
-        fetch(b + gridDim.x);
+        fetch_range(b + gridDim.x, std::integral_constant<int, EARLY>{}, std::integral_constant<int, TPW>{});
 
         // ---- natural-order write-out: y_u with u = M q + m; (q, m) advance by ST
         //      per step without a division
