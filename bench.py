@@ -3,8 +3,8 @@
 Headline step: one forward plus one adjoint transform of the ragged batch --
 10,000 blocks whose K is drawn from {64, 128, 256, 512, 1024} and M from
 {3, 5, 7, 9, 15}, seeded 64-QAM coefficients, one raised-cosine filter per
-block with roll-off U[0.1, 0.9] -- each direction one persistent launch
-replayed from a HIP graph, inputs resident in HBM.  It is the largest of the
+block with roll-off U[0.1, 0.9] -- each direction one launch (one workgroup
+per cost-ordered work item) replayed from a HIP graph, inputs resident in HBM.  It is the largest of the
 standard single-GPU batches (30.7 M points; 1.23 GB of algorithmic traffic
 per step, far above the 256 MB last-level cache).
 
@@ -193,7 +193,7 @@ def headline(args, T, W):
     # write y (8 B), per point
     alg = 20.0 * rb.points
     roof = _roofline(alg, fwd_ms, measured_traffic("ragged_forward_10000", "ragged"),
-                     "ragged_kernel (forward), one persistent launch from a HIP graph",
+                     "ragged_kernel (forward), one launch per direction from a HIP graph",
                      {"adjoint_kernel_ms": round(adj_ms, 5),
                       "timing": f"HIP events around {args.steps} back-to-back graph launches per direction"})
 
@@ -225,8 +225,8 @@ def headline(args, T, W):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic (seeded 64-QAM coefficients, per-block raised-cosine filters, roll-off U[0.1, 0.9])",
            "config": {"workload": "ragged: 10000 blocks, K in {64,128,256,512,1024}, M in {3,5,7,9,15} "
-                                  "(30.7 M points), per-block taps; forward + adjoint, one persistent "
-                                  "launch each from a HIP graph",
+                                  "(30.7 M points), per-block taps; forward + adjoint, one launch "
+                                  "each from a HIP graph",
                       "blocks": B, "points": rb.points, "taps": "per block", "buffer_sets": args.nbuf},
            "roofline": roof, "error": error}
     if not args.no_compare:

@@ -32,7 +32,7 @@ namespace bt {
 #ifndef BT_RAGGED_MIN_WAVES
 #define BT_RAGGED_MIN_WAVES 1
 #endif
-constexpr int RT = BT_RAGGED_RT;  // threads per workgroup of the persistent kernel
+constexpr int RT = BT_RAGGED_RT;  // threads per workgroup (one tile)
 
 struct RaggedItem {
     int cls;              // class index
@@ -273,7 +273,7 @@ __device__ __forceinline__ void ragged_chunk(const RaggedArgs &a, const RaggedIt
 }
 
 // ------------------------------------------------------------------ class table
-// radix plans of the length-K part inside the persistent kernel: radices of at
+// radix plans of the length-K part inside the ragged kernel: radices of at
 // most 16 keep the shared register allocation (the maximum over classes) low
 template <int K> struct RKPlan { using type = typename KPlan<K>::type; };
 template <> struct RKPlan<512> { using type = Radices<8, 8, 8>; };
