@@ -10,7 +10,10 @@
 // from a HIP graph as it is.  Each item runs its class's compiled tile body
 // (radix plan, threads per block, blocks per tile) with the same pass
 // machinery as the uniform kernel; within an item the next tile's inputs are
-// fetched while the current tile runs its LDS passes.
+// fetched while the current tile runs its LDS passes.  Workgroups have 512
+// threads, at most 128 VGPRs and at most 74 KB of LDS, so two of any class
+// share a CU; the (1024, 15) class, whose whole block would take 123 KB, runs
+// the half-block exchange body of bt_half.hpp.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -18,19 +21,21 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/blocktransform.h"
 #include "bt_api_internal.hpp"
 #include "bt_fused.hpp"
+#include "bt_half.hpp"
 
 namespace bt {
 
 #ifndef BT_RAGGED_RT
-#define BT_RAGGED_RT 1024
+#define BT_RAGGED_RT 512
 #endif
 #ifndef BT_RAGGED_MIN_WAVES
-#define BT_RAGGED_MIN_WAVES 1
+#define BT_RAGGED_MIN_WAVES 4
 #endif
 constexpr int RT = BT_RAGGED_RT;  // threads per workgroup (one tile)
 
@@ -272,6 +277,38 @@ __device__ __forceinline__ void ragged_chunk(const RaggedArgs &a, const RaggedIt
     if (zero_tap && a.div && a.status) *a.status = 1;
 }
 
+// The (1024, 15) class: one block per 512-thread workgroup with the half-block LDS exchange
+// body (61 KB of LDS instead of 123 KB, so that two workgroups of any class share a CU).  The
+// class's radix plan stays [15, 8, 8, 16] for the plan's tables: its pass-2 and pass-3 base roots
+// include the roots of the [15, 32, 32] passes.
+template <int M, int SIDE, bool TGR>
+__device__ __forceinline__ void ragged_half(const RaggedArgs &a, const RaggedItem &it, c32 *lds)
+{
+    static_assert(RT == 512, "one 512-thread block per workgroup");
+    constexpr int N = 1024 * M;
+    constexpr uint32_t CB = 8, FB = 4;
+    int tx = threadIdx.x;
+    asm volatile("" : "+v"(tx));
+    const c32 *tw = a.tw + a.tw_off[it.cls];
+    HalfThread<M> h;
+    // [M, 8, 8, 16]: pass 2 holds exp(2 pi i k / (64 M)) at tw[M + k], pass 3 exp(2 pi i k / N)
+    // at tw[9 M + k]
+    h.init(tx, tw + M, 2, tw + 9 * M);
+    bool zero_tap = false;
+    for (int q = 0; q < it.count; ++q) {
+        const int e = it.first + q;
+        const int64_t xo = uniform64(a.x_off[e]), to = uniform64(a.tap_off[e]);
+        const rsrc_t ri = make_rsrc(a.in + xo, N * CB), ro = make_rsrc(a.out + xo, N * CB);
+        const rsrc_t rt = make_rsrc(a.taps + to, N * FB);
+        if constexpr (TGR)
+            half_block<M, SIDE, true, true>(h, lds, ri, ro, rt, make_rsrc(a.aux + xo, N * CB),
+                                            make_rsrc(a.tapbar + xo, N * FB), a.div, true, zero_tap);
+        else
+            half_block<M, SIDE, true>(h, lds, ri, ro, rt, ro, ro, a.div, true, zero_tap);
+    }
+    if (zero_tap && a.div && a.status) *a.status = 1;
+}
+
 // ------------------------------------------------------------------ class table
 // radix plans of the length-K part inside the ragged kernel: radices of at
 // most 16 keep the shared register allocation (the maximum over classes) low
@@ -279,15 +316,14 @@ template <int K> struct RKPlan { using type = typename KPlan<K>::type; };
 template <> struct RKPlan<512> { using type = Radices<8, 8, 8>; };
 template <> struct RKPlan<1024> { using type = Radices<8, 8, 16>; };
 
-// Per-class fitting inside the 128-VGPR budget of a 1024-thread workgroup.
-// CEIL rounds the threads per block up to the next power of two above the
-// widest pass (fewer elements per thread); the PF_* flags say whether the
+// Per-class fitting inside the 128-VGPR budget of 512-thread workgroups at two
+// per CU.  CEIL rounds the threads per block up to the next power of two above
+// the widest pass (fewer elements per thread); the PF_* flags say whether the
 // forward / tap-gradient adjoint / plain adjoint prefetch the next tile (a
-// second copy of the pass-0 operands in registers).  Every forward and plain
-// adjoint body fits with the prefetch; the specialisations below keep CEIL
-// where it was measured to help and drop the prefetch from the tap-gradient
-// bodies that would otherwise spill (per-class VGPR and spill counts of the
-// compiler, one class compiled at a time).
+// second copy of the pass-0 operands in registers).  The specialisations keep
+// CEIL where it was measured to help and drop the prefetch from the bodies
+// that would otherwise spill (per-class VGPR and spill counts of the compiler,
+// one class compiled at a time); (1024, 9) goes without it in every direction.
 template <int K, int M> struct RTune {
     static constexpr bool CEIL = false;
     static constexpr bool PF_FWD = true, PF_TG = true, PF_ADJ = true;
@@ -301,10 +337,11 @@ BT_RTUNE(64, 9, true, true, true, true)
 BT_RTUNE(64, 15, false, true, false, true)
 BT_RTUNE(128, 15, false, true, false, true)
 BT_RTUNE(256, 15, false, true, false, true)
-BT_RTUNE(512, 9, true, true, true, true)
-BT_RTUNE(512, 15, true, true, true, true)
-BT_RTUNE(1024, 9, false, true, false, true)
-BT_RTUNE(1024, 15, false, true, false, true)
+BT_RTUNE(512, 9, true, true, false, true)
+BT_RTUNE(512, 15, true, true, false, true)
+BT_RTUNE(1024, 5, false, true, false, true)
+BT_RTUNE(1024, 7, false, true, false, true)
+BT_RTUNE(1024, 9, false, false, false, false)
 #undef BT_RTUNE
 
 template <int K, int M>
@@ -319,7 +356,9 @@ struct RClass {
     {
         return SIDE == SIDE_IN ? Tune::PF_FWD : (TGR ? Tune::PF_TG : Tune::PF_ADJ);
     }
-    static constexpr int lds() { return PL::count > 1 ? BPW * PL::total() * 8 : 0; }
+    // (1024, 15) runs the half-block exchange body
+    static constexpr bool HALF = K == 1024 && M == 15;
+    static constexpr int lds() { return HALF ? PL::total() / 2 * 8 : (PL::count > 1 ? BPW * PL::total() * 8 : 0); }
 };
 
 #ifndef BT_RAGGED_CLASSES
@@ -377,7 +416,12 @@ __global__ void __launch_bounds__(RT, BT_RAGGED_MIN_WAVES) ragged_kernel(RaggedA
 #define BT_CLASS_CASE(K_, M_)                                                                      \
     case class_index(K_, M_): {                                                                    \
         using C = RClass<K_, M_>;                                                                  \
-        ragged_chunk<typename C::PL, C::TB, C::BPW, SIDE, TGR, C::template pf<SIDE, TGR>()>(a, it, lds_dyn); \
+        if constexpr (C::HALF) {                                                                   \
+            static_assert(std::is_same<typename C::PL, Radices<M_, 8, 8, 16>>::value, "root table"); \
+            ragged_half<M_, SIDE, TGR>(a, it, lds_dyn);                                            \
+        } else {                                                                                   \
+            ragged_chunk<typename C::PL, C::TB, C::BPW, SIDE, TGR, C::template pf<SIDE, TGR>()>(a, it, lds_dyn); \
+        }                                                                                          \
         break;                                                                                     \
     }
         BT_RAGGED_CLASSES(BT_CLASS_CASE)
