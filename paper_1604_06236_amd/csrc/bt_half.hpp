@@ -183,8 +183,8 @@ __device__ __forceinline__ void half_block(const HalfThread<M> &h, c32 *L, rsrc_
     });
 
     // ---- pass 2: twiddle, DFT_32, output side, natural-order store of y[t + B1 r]
-    float tl[1][SIDE == SIDE_OUT ? 32 : 1];
-    if constexpr (SIDE == SIDE_OUT) {
+    float tl[1][SIDE == SIDE_OUT && !TGR ? 32 : 1];
+    if constexpr (SIDE == SIDE_OUT && !TGR) {
         static_for<0, 32>([&](auto rI) {
             constexpr int r = decltype(rI)::value;
             tl[0][r] = ld_f<NTT>(rt, uint32_t(j) * FB, r * B1 * FB);
@@ -198,18 +198,40 @@ __device__ __forceinline__ void half_block(const HalfThread<M> &h, c32 *L, rsrc_
     });
     twiddle<0, 32>(z, h.w2);
     dft<32>(z);
-    if constexpr (SIDE == SIDE_OUT) tap_factors(tl, div, Nf, zero_tap, [&](int) { return valid && h.has1; });
-    if (h.has1) {
-        static_for<0, 32>([&](auto rI) {
-            constexpr int r = decltype(rI)::value;
-            c32 w = CONJ ? conj(z[r]) : z[r];
-            if constexpr (TGR) {
-                const c32 sv = ld_c<NTA>(rx, uint32_t(t) * CB, r * B1 * CB);
-                st_f<NTA>(sv.x * w.x + sv.y * w.y, rg, uint32_t(t) * FB, r * B1 * FB);
+    if constexpr (TGR) {
+        // the taps and S in groups of 8 outputs, each group's loads issued after the previous
+        // group's stores (all 32 at once would hold 96 more registers next to z)
+        static_for<0, 4>([&](auto gI) {
+            constexpr int g = decltype(gI)::value;
+            float tg[1][8];
+            c32 sv[8];
+            static_for<0, 8>([&](auto rI) {
+                constexpr int r = 8 * g + decltype(rI)::value;
+                tg[0][r - 8 * g] = ld_f<NTT>(rt, uint32_t(j) * FB, r * B1 * FB);
+                sv[r - 8 * g] = ld_c<NTA>(rx, uint32_t(j) * CB, r * B1 * CB);
+            });
+            tap_factors(tg, div, Nf, zero_tap, [&](int) { return valid && h.has1; });
+            if (h.has1) {
+                static_for<0, 8>([&](auto rI) {
+                    constexpr int r = 8 * g + decltype(rI)::value;
+                    const c32 w = conj(z[r]);
+                    const c32 s_ = sv[r - 8 * g];
+                    st_f<NTA>(s_.x * w.x + s_.y * w.y, rg, uint32_t(t) * FB, r * B1 * FB);
+                    st_c<NTA>(scale(w, tg[0][r - 8 * g]), ro, uint32_t(t) * CB, r * B1 * CB);
+                });
             }
-            if constexpr (SIDE == SIDE_OUT) w = scale(w, tl[0][r]);
-            st_c<NTA>(w, ro, uint32_t(t) * CB, r * B1 * CB);
+            asm volatile("" ::: "memory");
         });
+    } else {
+        if constexpr (SIDE == SIDE_OUT) tap_factors(tl, div, Nf, zero_tap, [&](int) { return valid && h.has1; });
+        if (h.has1) {
+            static_for<0, 32>([&](auto rI) {
+                constexpr int r = decltype(rI)::value;
+                c32 w = CONJ ? conj(z[r]) : z[r];
+                if constexpr (SIDE == SIDE_OUT) w = scale(w, tl[0][r]);
+                st_c<NTA>(w, ro, uint32_t(t) * CB, r * B1 * CB);
+            });
+        }
     }
 }
 

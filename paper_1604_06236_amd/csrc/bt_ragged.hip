@@ -231,23 +231,30 @@ __device__ __forceinline__ void ragged_chunk(const RaggedArgs &a, const RaggedIt
                 }
             }
             if (PF && t + 1 < ntiles) fetch(next);
-            // operands of the last pass, fetched while the LDS passes run
-            float tl[SIDE == SIDE_OUT ? ITL : 1][SIDE == SIDE_OUT ? RL : 1];
-            c32 sl[TGR ? ITL : 1][TGR ? RL : 1];
+            // operands of the last pass, fetched while the LDS passes run; where the tap
+            // gradient's operands of the whole last pass would hold more than 48 registers
+            // across the passes (LATE), each iteration of the last pass fetches its own
+            // before its LDS reads instead
+            constexpr bool LATE = SIDE == SIDE_OUT && ITL * RL > 16;
+            constexpr bool TL = SIDE == SIDE_OUT && !LATE;
+            float tl[TL ? ITL : 1][TL ? RL : 1];
+            c32 sl[TGR && !LATE ? ITL : 1][TGR && !LATE ? RL : 1];
+            if constexpr (!LATE) {
 #pragma unroll
-            for (int i = 0; i < ITL; ++i) {
-                const int j = tid + i * TB;
-                if (FULLL || j < NBL) {
-                    static_for<0, RL>([&](auto rI) {
-                        constexpr int q = decltype(rI)::value;
-                        if constexpr (SIDE == SIDE_OUT) tl[i][q] = ld_f<NT>(cur.taps, j * FB, q * NSL * FB);
-                        if constexpr (TGR) sl[i][q] = ld_c<NT>(cur.aux, j * CB, q * NSL * CB);
-                    });
+                for (int i = 0; i < ITL; ++i) {
+                    const int j = tid + i * TB;
+                    if (FULLL || j < NBL) {
+                        static_for<0, RL>([&](auto rI) {
+                            constexpr int q = decltype(rI)::value;
+                            if constexpr (TL) tl[i][q] = ld_f<NT>(cur.taps, j * FB, q * NSL * FB);
+                            if constexpr (TGR) sl[i][q] = ld_c<NT>(cur.aux, j * CB, q * NSL * CB);
+                        });
+                    }
                 }
             }
             lds_barrier();
             lds_passes<PL, TB, 1, OPT>(L, tid, w1s);
-            if constexpr (SIDE == SIDE_OUT)
+            if constexpr (TL)
                 tap_factors(tl, a.div, Nf, zero_tap,
                             [&](int i) { return cur.valid && (FULLL || tid + i * TB < NBL); });
             constexpr int SLOTL = TwSlots<PL, TB, OPT>::off(NP - 1);
@@ -255,6 +262,15 @@ __device__ __forceinline__ void ragged_chunk(const RaggedArgs &a, const RaggedIt
             for (int i = 0; i < ITL; ++i) {
                 const int j = tid + i * TB;
                 if (FULLL || j < NBL) {
+                    c32 si[LATE && TGR ? RL : 1];
+                    float ti[1][LATE ? RL : 1];
+                    if constexpr (LATE) {
+                        static_for<0, RL>([&](auto rI) {
+                            constexpr int q = decltype(rI)::value;
+                            if constexpr (TGR) si[q] = ld_c<NT>(cur.aux, j * CB, q * NSL * CB);
+                            ti[0][q] = ld_f<NT>(cur.taps, j * FB, q * NSL * FB);
+                        });
+                    }
                     c32 v[RL];
                     static_for<0, RL>([&](auto rI) {
                         constexpr int q = decltype(rI)::value;
@@ -262,11 +278,17 @@ __device__ __forceinline__ void ragged_chunk(const RaggedArgs &a, const RaggedIt
                     });
                     twiddle<OPT, RL>(v, w1s[SLOTL + i]);
                     dft<RL>(v);
+                    if constexpr (LATE) tap_factors(ti, a.div, Nf, zero_tap, [&](int) { return cur.valid; });
                     static_for<0, RL>([&](auto rI) {
                         constexpr int q = decltype(rI)::value;
                         c32 w = CONJ ? conj(v[q]) : v[q];
-                        if constexpr (TGR) st_f<NT>(sl[i][q].x * w.x + sl[i][q].y * w.y, cur.tg, j * FB, q * NSL * FB);
-                        if constexpr (SIDE == SIDE_OUT) w = scale(w, tl[i][q]);
+                        if constexpr (LATE) {
+                            if constexpr (TGR) st_f<NT>(si[q].x * w.x + si[q].y * w.y, cur.tg, j * FB, q * NSL * FB);
+                            w = scale(w, ti[0][q]);
+                        } else {
+                            if constexpr (TGR) st_f<NT>(sl[i][q].x * w.x + sl[i][q].y * w.y, cur.tg, j * FB, q * NSL * FB);
+                            if constexpr (SIDE == SIDE_OUT) w = scale(w, tl[i][q]);
+                        }
                         st_c<NT>(w, cur.out, j * CB, q * NSL * CB);
                     });
                 }
