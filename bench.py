@@ -609,8 +609,9 @@ def profile_workload(name, reps, T, W):
         return
     if name == "ragged_class":
         # one (K, M) class of the ragged batch (BT_CLASS="KxM", default 128x15), about 250 MB
-        # per array with per-block taps: the ragged kernel and then the uniform fused kernel
-        # on the same data, `reps` forward launches each
+        # per array with per-block taps: the ragged kernel (`reps` launches of the forward,
+        # the adjoint and the adjoint with tap gradient) and then `reps` launches of the
+        # uniform fused forward on the same data
         K, M = (int(v) for v in os.environ.get("BT_CLASS", "128x15").split("x"))
         N = K * M
         B = int(250e6 // (N * 8))
@@ -621,15 +622,21 @@ def profile_workload(name, reps, T, W):
         off = np.arange(B, dtype=np.int64) * N
         plan = T.RaggedPlan(np.full(B, K), np.full(B, M), off, off, B * N)
         fr = plan.bind("forward", S.view(-1), taps.view(-1), y.view(-1))
-        for _ in range(reps):
-            fr()
+        sb = torch.empty_like(S)
+        tb = torch.empty(B * N, dtype=torch.float32, device=dev)
+        ar = plan.bind("adjoint", y.view(-1), taps.view(-1), sb.view(-1))
+        gr = plan.bind("adjoint", y.view(-1), taps.view(-1), sb.view(-1), aux=S.view(-1), taps_bar=tb)
+        for f in (fr, ar, gr):
+            for _ in range(reps):
+                f()
         torch.cuda.synchronize()
         ff = T.bind_forward(S, taps, K, M, y)
         for _ in range(reps):
             ff()
         torch.cuda.synchronize()
         plan.close()
-        print(f"ragged_class: {reps} x ragged forward, then {reps} x fused forward, {B} blocks of ({K}, {M})",
+        print(f"ragged_class: {reps} x ragged forward, adjoint, tap-gradient adjoint, then {reps} x fused "
+              f"forward, {B} blocks of ({K}, {M})",
               flush=True)
         return
     if name == "nufft":

@@ -106,6 +106,9 @@ __device__ __forceinline__ void half_block(const HalfThread<M> &h, c32 *L, rsrc_
     constexpr bool CONJ = SIDE == SIDE_OUT;
     static_assert(B1 <= 512, "one pass-1 butterfly per thread");
     static_assert(!TGR || SIDE == SIDE_OUT, "tap gradient on the output side only");
+    // the output side holds its taps (and S) next to pass 2's values: sequential twiddle
+    // powers there need fewer registers than the squaring tree
+    constexpr int TWO = SIDE == SIDE_OUT ? OPT_SEQ_TWIDDLE : 0;
     const float Nf = float(N);
     const int t = h.t, j = h.j;
 
@@ -150,7 +153,7 @@ __device__ __forceinline__ void half_block(const HalfThread<M> &h, c32 *L, rsrc_
     });
 
     // ---- pass 1; its outputs in the order the exchange sends them
-    twiddle<0, 32>(v, h.w1);
+    twiddle<TWO, 32>(v, h.w1);
     dft<32>(v);
     c32 x0[16], x1[16];
     static_for<0, 16>([&](auto sI) {
@@ -196,28 +199,28 @@ __device__ __forceinline__ void half_block(const HalfThread<M> &h, c32 *L, rsrc_
         z[2 * s] = blend(z0[s], z1[s], h.odd_mask);
         z[2 * s + 1] = blend(z1[s], z0[s], h.odd_mask);
     });
-    twiddle<0, 32>(z, h.w2);
+    twiddle<TWO, 32>(z, h.w2);
     dft<32>(z);
     if constexpr (TGR) {
-        // the taps and S in groups of 8 outputs, each group's loads issued after the previous
+        // the taps and S in groups of 4 outputs, each group's loads issued after the previous
         // group's stores (all 32 at once would hold 96 more registers next to z)
-        static_for<0, 4>([&](auto gI) {
+        static_for<0, 8>([&](auto gI) {
             constexpr int g = decltype(gI)::value;
-            float tg[1][8];
-            c32 sv[8];
-            static_for<0, 8>([&](auto rI) {
-                constexpr int r = 8 * g + decltype(rI)::value;
-                tg[0][r - 8 * g] = ld_f<NTT>(rt, uint32_t(j) * FB, r * B1 * FB);
-                sv[r - 8 * g] = ld_c<NTA>(rx, uint32_t(j) * CB, r * B1 * CB);
+            float tg[1][4];
+            c32 sv[4];
+            static_for<0, 4>([&](auto rI) {
+                constexpr int r = 4 * g + decltype(rI)::value;
+                tg[0][r - 4 * g] = ld_f<NTT>(rt, uint32_t(j) * FB, r * B1 * FB);
+                sv[r - 4 * g] = ld_c<NTA>(rx, uint32_t(j) * CB, r * B1 * CB);
             });
             tap_factors(tg, div, Nf, zero_tap, [&](int) { return valid && h.has1; });
             if (h.has1) {
-                static_for<0, 8>([&](auto rI) {
-                    constexpr int r = 8 * g + decltype(rI)::value;
+                static_for<0, 4>([&](auto rI) {
+                    constexpr int r = 4 * g + decltype(rI)::value;
                     const c32 w = conj(z[r]);
-                    const c32 s_ = sv[r - 8 * g];
+                    const c32 s_ = sv[r - 4 * g];
                     st_f<NTA>(s_.x * w.x + s_.y * w.y, rg, uint32_t(t) * FB, r * B1 * FB);
-                    st_c<NTA>(scale(w, tg[0][r - 8 * g]), ro, uint32_t(t) * CB, r * B1 * CB);
+                    st_c<NTA>(scale(w, tg[0][r - 4 * g]), ro, uint32_t(t) * CB, r * B1 * CB);
                 });
             }
             asm volatile("" ::: "memory");

@@ -429,7 +429,10 @@ static const ClassInfo *class_table(int *count)
 template <int SIDE, bool TGR>
 __global__ void __launch_bounds__(RT, BT_RAGGED_MIN_WAVES) ragged_kernel(RaggedArgs a)
 {
-    extern __shared__ c32 lds_dyn[];
+    // 16-byte alignment lets the compiler pair each thread's LDS accesses into 64-bit
+    // two-address instructions (with the 4-byte alignment of the element type it issues one
+    // two-dword instruction per complex value: twice the LDS instructions)
+    extern __shared__ __attribute__((aligned(16))) c32 lds_dyn[];
     poison_lds(lds_dyn, a.lds_elems);
     const RaggedItem it = a.items[blockIdx.x];
     // one switch (a scalar compare tree) rather than a chain of tests whose merges the
