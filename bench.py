@@ -41,7 +41,7 @@ MFMA_BF16_PEAK = 2.5e15
 TOL = 1e-5
 # sources each roofline's counter entry in profiles/traffic.json was taken on
 KERNEL_SOURCES = {
-    "ragged": ("bt_ragged.hip", "bt_fused.hpp", "bt_dft.hpp"),
+    "ragged": ("bt_ragged.hip", "bt_half.hpp", "bt_fused.hpp", "bt_dft.hpp"),
     "fused": ("bt_fused.hpp", "bt_dft.hpp"),
 }
 PROFILE_WORKLOADS = ("ragged", "ragged_class", "plain_gpu", "precision", "split_bf16", "split_fp16",
