@@ -326,7 +326,7 @@ def inverse(y, taps, K, M):
 
 # ------------------------------------------------------------------ ragged batches
 class RaggedPlan:
-    """Persistent-kernel plan for a batch of blocks with their own (K, M).
+    """Plan for a batch of blocks with their own (K, M), run as one grouped launch per call.
 
     `K`, `M`, `x_off`, `tap_off` are host arrays (one entry per block; offsets in
     elements of the flat complex / tap arrays); `total_points` is the length of
