@@ -251,6 +251,21 @@ int transform_ragged_execute(tf_ragged_plan plan, int32_t direction, const void 
                              const float *taps, void *out, const void *aux, float *taps_bar,
                              int32_t *status_dev, int32_t use_graph, void *stream);
 
+/* Autotuned choice of the ragged kernel's tile pipelining, per class (K, M) and body:
+   body 0 is the input side (forward), 1 the output side (inverse, adjoint), 2 the adjoint with
+   the per-block tap gradient.  prefetch = 0 makes the class's tiles fetch their pass-0 operands
+   when they start; 1 (or -1, the compiled default) fetches each tile's operands while the
+   previous tile of the work item runs its LDS passes, where that body is compiled with the
+   prefetch (it is where it fits the kernel's register budget).  Both forms compute the same
+   arithmetic; as they are compiled separately, results may differ in rounding (relative
+   differences near 1e-7).  The choice is process-wide and taken by plans created
+   afterwards.  Returns TF_EINVAL for a body or prefetch value out of range, TF_EUNSUPPORTED for
+   a (K, M) outside the 25 classes or prefetch = 1 where the body has no prefetching form (the
+   (1024, 15) half-block body has none; `transform_ragged_prefetch_selected` reports which). */
+int transform_ragged_prefetch_select(int32_t K, int32_t M, int32_t body, int32_t prefetch);
+/* The prefetch setting in effect for (K, M, body): *prefetch = 0 or 1. */
+int transform_ragged_prefetch_selected(int32_t K, int32_t M, int32_t body, int32_t *prefetch);
+
 /* ---------------------------------------------------------------------------
  * Non-iterative type-5 and type-4 NFFT methods (Secs. "Computation of the
  * type-5 NFFT" / "Computation of the type-4 NFFT"), batched over independent

@@ -39,6 +39,7 @@ EXPORTED = (
     "nudft_type1", "nudft_type2", "nufft_workspace_size_ex", "nufft_solve", "nufft_setup", "nufft_apply",
     "nfft_workspace_size",
     "nfft_type1", "nfft_type2", "transform_adjoint_noalloc", "transform_noalloc_scratch_bytes",
+    "transform_ragged_prefetch_select", "transform_ragged_prefetch_selected",
 )
 
 _lib = None
@@ -89,6 +90,8 @@ def load() -> ctypes.CDLL:
     lib.transform_ragged_plan_create_ex.argtypes = [vp, vp, vp, vp, i64, i64, i32, ctypes.POINTER(vp)]
     lib.transform_ragged_plan_destroy.argtypes = [vp]
     lib.transform_ragged_execute.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, i32, vp]
+    lib.transform_ragged_prefetch_select.argtypes = [i32, i32, i32, i32]
+    lib.transform_ragged_prefetch_selected.argtypes = [i32, i32, i32, ctypes.POINTER(i32)]
     lib.nufft_workspace_size.argtypes = [i64, i32, i32]
     lib.nufft_workspace_size.restype = sz
     lib.nufft_type5.argtypes = [vp, vp, vp, i64, i32, i32, ctypes.c_double, vp, sz, vp]

@@ -8,6 +8,9 @@ JSON ({"K,M": [schedule, grid_cap]}), which `transform` loads at import from
 $BT_SCHEDULES or from schedules.json next to this file.
 
     python -m paper_1604_06236_amd.autotune --out schedules.json
+
+The ragged kernel's work-item size and its per-class tile pipelining (prefetch on or off
+per class and body) are tuned and saved alongside.
 """
 from __future__ import annotations
 
@@ -109,14 +112,100 @@ def tune_ragged(T, W, chunks=(1, 2, 3, 4, 6, 8), reps=10, verbose=True):
     return best, results
 
 
+RAGGED_CLASSES = [(K, M) for K in (64, 128, 256, 512, 1024) for M in (3, 5, 7, 9, 15)]
+
+
+def tune_ragged_prefetch(T, classes=RAGGED_CLASSES, reps=20, verbose=True):
+    """For each class of the ragged kernel and each of its three bodies (0 forward, 1 output
+    side, 2 adjoint with tap gradient) that has a prefetching form, time a single-class batch
+    (per-block taps, about 250 MB per array) with the prefetch on and off and select the faster.
+    Returns {"K,M": [choice per body]} (0 off, 1 on) and every timing."""
+    import numpy as np
+    import torch
+    dev = "cuda"
+    choice, report = {}, {}
+    for K, M in classes:
+        for b in range(3):
+            T.ragged_prefetch_select(K, M, b, -1)
+        on = [T.ragged_prefetch_selected(K, M, b) for b in range(3)]
+        if not any(on):
+            continue
+        N = K * M
+        B = int(250e6 // (N * 8))
+        g = torch.Generator(device=dev).manual_seed(K * 64 + M)
+        S = torch.randn(B * N, dtype=torch.complex64, device=dev, generator=g)
+        taps = torch.rand(B * N, device=dev, generator=g) + 0.5
+        y = S.clone()
+        sb = torch.empty_like(S)
+        tb = torch.empty(B * N, dtype=torch.float32, device=dev)
+        off = np.arange(B, dtype=np.int64) * N
+        sel = []
+        for b in range(3):
+            if not on[b]:
+                sel.append(0)
+                continue
+            times = {}
+            for pf in (1, 0):
+                T.ragged_prefetch_select(K, M, b, pf)
+                plan = T.RaggedPlan(np.full(B, K), np.full(B, M), off, off, B * N)
+                if b == 0:
+                    call = plan.bind("forward", S, taps, y)
+                elif b == 1:
+                    call = plan.bind("adjoint", y, taps, sb)
+                else:
+                    call = plan.bind("adjoint", y, taps, sb, aux=S, taps_bar=tb)
+                best = float("inf")
+                for _ in range(3):
+                    for _ in range(2):
+                        call()
+                    ev0 = torch.cuda.Event(enable_timing=True)
+                    ev1 = torch.cuda.Event(enable_timing=True)
+                    ev0.record()
+                    for _ in range(reps):
+                        call()
+                    ev1.record()
+                    torch.cuda.synchronize()
+                    best = min(best, ev0.elapsed_time(ev1) * 1e3 / reps)
+                plan.close()
+                times[pf] = best
+            pick = 1 if times[1] <= times[0] else 0
+            T.ragged_prefetch_select(K, M, b, pick)
+            sel.append(pick)
+            report[f"{K},{M},{b}"] = {"us_prefetch": round(times[1], 2), "us_no_prefetch": round(times[0], 2)}
+            if verbose:
+                print(f"ragged ({K}, {M}) body {b}: prefetch {times[1]:.1f} us, without {times[0]:.1f} us "
+                      f"-> {'on' if pick else 'off'}", flush=True)
+        choice[f"{K},{M}"] = sel
+        del S, taps, y, sb, tb
+        torch.cuda.empty_cache()
+    return choice, report
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=None, help="write the selections here (JSON)")
     ap.add_argument("--report", default=None, help="write every timing here (JSON)")
     ap.add_argument("--reps", type=int, default=50)
+    ap.add_argument("--only-ragged-prefetch", action="store_true",
+                    help="tune only the ragged kernel's per-class prefetch, keeping the other "
+                         "selections of --out (or of the loaded schedules)")
     args = ap.parse_args()
     from paper_1604_06236_amd import transform as T
     from paper_1604_06236_amd import _native as nat
+    if args.only_ragged_prefetch:
+        choice, report = tune_ragged_prefetch(T)
+        if args.out:
+            src = args.out if os.path.exists(args.out) else os.path.join(
+                os.path.dirname(os.path.abspath(__file__)), "schedules.json")
+            with open(src) as f:
+                sel = json.load(f)
+            sel["ragged_prefetch"] = choice
+            with open(args.out, "w") as f:
+                json.dump(sel, f, indent=1)
+        if args.report:
+            with open(args.report, "w") as f:
+                json.dump(report, f, indent=1)
+        return
     report = {}
     for K, M, B in STANDARD:
         best, res = tune_shape(T, K, M, B, reps=args.reps)
@@ -126,6 +215,8 @@ def main():
     from paper_1604_06236_amd import workloads as W
     best_r, res_r = tune_ragged(T, W)
     report["ragged"] = {"best": best_r, "all": res_r}
+    pf_r, pf_rep = tune_ragged_prefetch(T)
+    report["ragged_prefetch"] = pf_rep
     print(f"best for ragged: chunk_tiles {best_r['chunk_tiles']} ({best_r['us_fwd_adj']} us, "
           f"{best_r['GBps']} GB/s)", flush=True)
     if args.out:
@@ -133,6 +224,7 @@ def main():
         with open(args.out) as f:
             sel = json.load(f)
         sel["ragged_chunk_tiles"] = best_r["chunk_tiles"]
+        sel["ragged_prefetch"] = pf_r
         with open(args.out, "w") as f:
             json.dump(sel, f, indent=1)
     if args.report:

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -43,7 +44,8 @@ struct RaggedItem {
     int cls;              // class index
     int first;            // first entry in the block order
     int count;            // blocks in this chunk (tiles of BPW blocks of the class)
-    int pad;
+    int pf;               // bit d: prefetch the next tile in body d (0 input side: forward;
+                          // 1 output side: inverse, adjoint; 2 adjoint with tap gradient)
 };
 
 struct RaggedArgs {
@@ -373,10 +375,12 @@ struct RClass {
     static constexpr int TB0 = Tune::CEIL ? 2 * pow2_floor(PL::max_nb() - 1) : pow2_floor(PL::max_nb());
     static constexpr int TB = TB0 < 64 ? 64 : (TB0 > RT ? RT : TB0);
     static constexpr int BPW = RT / TB;
-    template <int SIDE, bool TGR>
-    static constexpr bool pf()
+    // default prefetch bits (bit d for body d): the bodies that are also
+    // compiled with the prefetch (where it fits the register budget); plans take these unless
+    // an autotuned choice turns the prefetch off
+    static constexpr int pf_default()
     {
-        return SIDE == SIDE_IN ? Tune::PF_FWD : (TGR ? Tune::PF_TG : Tune::PF_ADJ);
+        return (Tune::PF_FWD ? 1 : 0) | (Tune::PF_ADJ ? 2 : 0) | (Tune::PF_TG ? 4 : 0);
     }
     // (1024, 15) runs the half-block exchange body
     static constexpr bool HALF = K == 1024 && M == 15;
@@ -402,7 +406,7 @@ constexpr int class_index(int K, int M)
 }
 
 struct ClassInfo {
-    int K, M, N, TB, BPW, lds, npass;
+    int K, M, N, TB, BPW, lds, npass, pf, half;   // pf: default prefetch bits; half: half-block body
     int radix[8];
 };
 
@@ -413,7 +417,8 @@ static const ClassInfo *class_table(int *count)
 #define BT_CLASS_INFO(K_, M_)                                                               \
     {                                                                                       \
         using C = RClass<K_, M_>;                                                           \
-        ClassInfo c{K_, M_, K_ * M_, C::TB, C::BPW, C::lds(), C::PL::count, {}};            \
+        ClassInfo c{K_, M_, K_ * M_, C::TB, C::BPW, C::lds(), C::PL::count,                 \
+                    C::HALF ? 0 : C::pf_default(), C::HALF ? 1 : 0, {}};                    \
         for (int i = 0; i < C::PL::count; ++i) c.radix[i] = C::PL::get(i);                  \
         v.push_back(c);                                                                     \
     }
@@ -435,6 +440,7 @@ __global__ void __launch_bounds__(RT, BT_RAGGED_MIN_WAVES) ragged_kernel(RaggedA
     extern __shared__ __attribute__((aligned(16))) c32 lds_dyn[];
     poison_lds(lds_dyn, a.lds_elems);
     const RaggedItem it = a.items[blockIdx.x];
+    constexpr int DIR = SIDE == SIDE_IN ? 0 : (TGR ? 2 : 1);   // body index of the prefetch bits
     // one switch (a scalar compare tree) rather than a chain of tests whose merges the
     // compiler carries as predicate masks through every class
     switch (it.cls) {
@@ -444,8 +450,13 @@ __global__ void __launch_bounds__(RT, BT_RAGGED_MIN_WAVES) ragged_kernel(RaggedA
         if constexpr (C::HALF) {                                                                   \
             static_assert(std::is_same<typename C::PL, Radices<M_, 8, 8, 16>>::value, "root table"); \
             ragged_half<M_, SIDE, TGR>(a, it, lds_dyn);                                            \
+        } else if constexpr ((C::pf_default() >> DIR) & 1) {                                      \
+            if ((it.pf >> DIR) & 1)                                                                \
+                ragged_chunk<typename C::PL, C::TB, C::BPW, SIDE, TGR, true>(a, it, lds_dyn);      \
+            else                                                                                   \
+                ragged_chunk<typename C::PL, C::TB, C::BPW, SIDE, TGR, false>(a, it, lds_dyn);     \
         } else {                                                                                   \
-            ragged_chunk<typename C::PL, C::TB, C::BPW, SIDE, TGR, C::template pf<SIDE, TGR>()>(a, it, lds_dyn); \
+            ragged_chunk<typename C::PL, C::TB, C::BPW, SIDE, TGR, false>(a, it, lds_dyn);         \
         }                                                                                          \
         break;                                                                                     \
     }
@@ -523,6 +534,58 @@ static const void *ragged_kernel_ptr(int side, bool tg)
               : reinterpret_cast<const void *>(&ragged_kernel<SIDE_OUT, false>);
 }
 
+// autotuned prefetch choices per class and body (0 input side, 1 output side, 2 output side
+// with tap gradient): -1 (compiled default), 0 (off) or 1 (on, where the default is on)
+static std::mutex g_pf_mu;
+static std::vector<std::array<int8_t, 3>> g_pf_choice;
+
+static int class_of(int32_t K, int32_t M)
+{
+    int ncls = 0;
+    const ClassInfo *cls = class_table(&ncls);
+    for (int c = 0; c < ncls; ++c)
+        if (cls[c].K == K && cls[c].M == M) return c;
+    return -1;
+}
+
+// prefetch bits of class c in effect (caller holds g_pf_mu)
+static int pf_bits(int c)
+{
+    int ncls = 0;
+    const ClassInfo *cls = class_table(&ncls);
+    if (cls[c].half) return 0;   // the half-block body has no prefetch variant
+    int bits = cls[c].pf;
+    if (g_pf_choice.size() == size_t(ncls))
+        for (int d = 0; d < 3; ++d)
+            if (g_pf_choice[c][d] == 0) bits &= ~(1 << d);
+    return bits;
+}
+
+extern "C" int transform_ragged_prefetch_select(int32_t K, int32_t M, int32_t body, int32_t prefetch)
+{
+    if (body < 0 || body > 2 || prefetch < -1 || prefetch > 1) return TF_EINVAL;
+    const int c = class_of(K, M);
+    if (c < 0) return TF_EUNSUPPORTED;
+    int ncls = 0;
+    const ClassInfo *cls = class_table(&ncls);
+    // a prefetching body exists only where the compiled default prefetches
+    if (prefetch == 1 && !((cls[c].pf >> body) & 1)) return TF_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_pf_mu);
+    if (g_pf_choice.size() != size_t(ncls)) g_pf_choice.assign(size_t(ncls), {int8_t(-1), int8_t(-1), int8_t(-1)});
+    g_pf_choice[c][body] = int8_t(prefetch);
+    return TF_OK;
+}
+
+extern "C" int transform_ragged_prefetch_selected(int32_t K, int32_t M, int32_t body, int32_t *prefetch)
+{
+    if (body < 0 || body > 2 || !prefetch) return TF_EINVAL;
+    const int c = class_of(K, M);
+    if (c < 0) return TF_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_pf_mu);
+    *prefetch = (pf_bits(c) >> body) & 1;
+    return TF_OK;
+}
+
 extern "C" int transform_ragged_plan_create(const int32_t *K, const int32_t *M, const int64_t *x_off,
                                             const int64_t *tap_off, int64_t nblocks,
                                             int64_t total_points, tf_ragged_plan *plan)
@@ -565,12 +628,18 @@ extern "C" int transform_ragged_plan_create_ex(const int32_t *K, const int32_t *
     std::vector<int> order;
     std::vector<RaggedItem> items;
     std::vector<double> cost;
+    std::vector<int> pf(ncls, 0);
+    {
+        std::lock_guard<std::mutex> lk(g_pf_mu);
+        for (int c = 0; c < ncls; ++c) pf[c] = pf_bits(c);
+    }
     for (int c = 0; c < ncls; ++c) {
         if (members[c].empty()) continue;
         const size_t per_chunk = size_t(cls[c].BPW) * chunk_tiles;
         for (size_t s = 0; s < members[c].size(); s += per_chunk) {
             RaggedItem it{};
             it.cls = c;
+            it.pf = pf[c];
             it.first = int(order.size());
             it.count = int(std::min<size_t>(per_chunk, members[c].size() - s));
             for (int q = 0; q < it.count; ++q) order.push_back(members[c][s + q]);

@@ -28,8 +28,10 @@ _RAGGED_CHUNK = 0      # tiles per ragged work item (0: automatic)
 def load_schedules(path: Optional[str] = None) -> bool:
     """Apply autotuned schedule choices from a JSON file ($BT_SCHEDULES, or
     schedules.json next to this module): per-(K, M) schedules go to the library,
-    the ragged work-item size ("ragged_chunk_tiles") to RaggedPlan.  Returns True
-    when a file was applied."""
+    the ragged work-item size ("ragged_chunk_tiles") to RaggedPlan and the ragged
+    per-class prefetch choices ("ragged_prefetch": {"K,M": [forward, output side,
+    tap gradient]}, 0 off / 1 on) to the library.  Returns True when a file was
+    applied."""
     import json
     import os
     global _RAGGED_CHUNK
@@ -39,10 +41,32 @@ def load_schedules(path: Optional[str] = None) -> bool:
         return False
     try:
         with open(path) as f:
-            _RAGGED_CHUNK = int(json.load(f).get("ragged_chunk_tiles", 0))
+            sel = json.load(f)
+        _RAGGED_CHUNK = int(sel.get("ragged_chunk_tiles", 0))
+        for km, bodies in sel.get("ragged_prefetch", {}).items():
+            K, M = (int(v) for v in km.split(","))
+            for body, on in enumerate(bodies):
+                # a choice this build cannot honour (no such class or body) keeps the default
+                nat.load().transform_ragged_prefetch_select(K, M, body, int(on))
     except (OSError, ValueError, TypeError):
         _RAGGED_CHUNK = 0
     return nat.load().transform_load_schedule(path.encode()) == nat.TF_OK
+
+
+def ragged_prefetch_select(K: int, M: int, body: int, prefetch: int):
+    """Per-class tile pipelining of the ragged kernel for plans created afterwards: body 0
+    forward, 1 inverse / adjoint, 2 adjoint with tap gradient; prefetch 0 off, 1 on (where
+    that body has a prefetching form), -1 the compiled default."""
+    nat.check("transform_ragged_prefetch_select",
+              nat.load().transform_ragged_prefetch_select(K, M, body, prefetch))
+
+
+def ragged_prefetch_selected(K: int, M: int, body: int) -> int:
+    """The prefetch setting in effect for (K, M, body): 0 or 1."""
+    v = ctypes.c_int32(0)
+    nat.check("transform_ragged_prefetch_selected",
+              nat.load().transform_ragged_prefetch_selected(K, M, body, ctypes.byref(v)))
+    return int(v.value)
 
 
 load_schedules()
@@ -52,6 +76,7 @@ __all__ = [
     "transform_prepare", "workspace_size", "schedules", "select_schedule", "Transform",
     "InverseTransform", "forward", "inverse", "RaggedPlan", "bind_forward", "bind_adjoint",
     "selected_schedule", "transform_decimated", "transform_decimated_adjoint",
+    "ragged_prefetch_select", "ragged_prefetch_selected",
 ]
 
 

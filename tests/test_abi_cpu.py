@@ -106,6 +106,32 @@ def test_schedule_registry(lib, tmp_path):
     assert lib.transform_schedule_select(128, 15, -1, 0) == nat.TF_OK
 
 
+def test_ragged_prefetch_registry(lib):
+    """Per-class tile-pipelining choices of the ragged kernel: host-side table only."""
+    import ctypes
+    v = ctypes.c_int32(-7)
+    sel = lambda K, M, b: (lib.transform_ragged_prefetch_selected(K, M, b, ctypes.byref(v)), v.value)
+    assert lib.transform_ragged_prefetch_select(128, 15, 3, 0) == nat.TF_EINVAL       # body
+    assert lib.transform_ragged_prefetch_select(128, 15, 0, 2) == nat.TF_EINVAL       # value
+    assert lib.transform_ragged_prefetch_select(32, 15, 0, 0) == nat.TF_EUNSUPPORTED  # no such class
+    assert lib.transform_ragged_prefetch_selected(128, 15, 0, None) == nat.TF_EINVAL
+    # the (1024, 15) half-block body has no prefetching form
+    assert sel(1024, 15, 0) == (nat.TF_OK, 0)
+    assert lib.transform_ragged_prefetch_select(1024, 15, 0, 1) == nat.TF_EUNSUPPORTED
+    # (128, 15) forward prefetches by default; off, then back to the default
+    assert lib.transform_ragged_prefetch_select(128, 15, 0, -1) == nat.TF_OK
+    assert sel(128, 15, 0) == (nat.TF_OK, 1)
+    assert lib.transform_ragged_prefetch_select(128, 15, 0, 0) == nat.TF_OK
+    assert sel(128, 15, 0) == (nat.TF_OK, 0)
+    assert sel(128, 15, 1) == (nat.TF_OK, 1)                  # other bodies untouched
+    assert lib.transform_ragged_prefetch_select(128, 15, 0, 1) == nat.TF_OK
+    assert sel(128, 15, 0) == (nat.TF_OK, 1)
+    # (128, 15) with the tap gradient has no prefetching form (it would spill)
+    assert sel(128, 15, 2) == (nat.TF_OK, 0)
+    assert lib.transform_ragged_prefetch_select(128, 15, 2, 1) == nat.TF_EUNSUPPORTED
+    assert lib.transform_ragged_prefetch_select(128, 15, 2, 0) == nat.TF_OK
+
+
 def test_workspace_sizes_host_only(lib):
     assert lib.transform_workspace_size(10, 16, 5, 0, 0, 0) == 0
     # plain path: two complex buffers, plus tap-gradient rows when shared

@@ -179,6 +179,56 @@ def test_ragged_chunk_sizes_agree(T):
         assert np.array_equal(o.view(np.uint64), outs[0].view(np.uint64))
 
 
+def test_ragged_prefetch_choices_agree(T):
+    """The per-class tile pipelining (prefetch of the next tile on or off, chosen by the
+    autotuner) only moves loads in time: forward, inverse, adjoint and the tap-gradient adjoint
+    match the oracle either way, and agree with each other to rounding (the two forms of a body
+    are compiled separately, so the compiler may contract different multiply-adds)."""
+    lay, S, taps = W.make_ragged("ragged", nblocks=600)      # several tiles per item per class
+    dS, dt = _dev(S), _dev(taps)
+    yb = W.cn01(np.random.default_rng(9), lay.total).astype(np.complex64)
+    dyb = _dev(yb)
+    classes = sorted(set(zip(lay.K.tolist(), lay.M.tolist())))
+    print(f"case ragged prefetch choices, blocks=600, classes={len(classes)}", flush=True)
+
+    def run():
+        plan = T.RaggedPlan(lay.K, lay.M, lay.x_off, lay.tap_off, lay.total, chunk_tiles=4)
+        y = _host(plan.execute("forward", dS, dt, use_graph=False))
+        inv = _host(plan.execute("inverse", dyb, dt, use_graph=False))
+        sb, tb = plan.execute("adjoint", dyb, dt, aux=dS, want_taps_bar=True, use_graph=False)
+        sb0 = _host(plan.execute("adjoint", dyb, dt, use_graph=False))
+        out = (y, inv, _host(sb), _host(tb), sb0)
+        plan.close()
+        return out
+
+    try:
+        for K, M in classes:
+            for b in range(3):
+                T.ragged_prefetch_select(K, M, b, -1)
+        assert any(T.ragged_prefetch_selected(K, M, b) for K, M in classes for b in range(3))
+        ref = run()
+        for K, M in classes:
+            for b in range(3):
+                T.ragged_prefetch_select(K, M, b, 0)
+        off = run()
+    finally:
+        for K, M in classes:
+            for b in range(3):
+                T.ragged_prefetch_select(K, M, b, -1)
+        T.load_schedules()
+    y_ref = O.forward_ragged(lay.N, lay.x_off, lay.tap_off, S, taps)
+    inv_ref = O.inverse_ragged(lay.N, lay.x_off, lay.tap_off, yb, taps)
+    sb_ref, tb_ref = O.adjoint_ragged(lay.N, lay.x_off, lay.tap_off, yb, taps, S)
+    for out in (ref, off):
+        y, inv, sb, tb, sb0 = out
+        assert rel_l2(y, y_ref) < TOL and per_block_max(y, y_ref, lay) < TOL
+        assert rel_l2(inv, inv_ref) < TOL and per_block_max(inv, inv_ref, lay) < TOL
+        assert rel_l2(sb, sb_ref) < TOL and rel_l2(sb0, sb_ref) < TOL
+        assert rel_l2(tb, tb_ref) < TOL
+    for a, b in zip(ref, off):
+        assert rel_l2(a, b.astype(np.complex128)) < 1e-6
+
+
 def test_ragged_plan_on_two_streams(T):
     """One plan executed on two streams at once (forward on one, adjoint on the other, eager
     and graph-replayed): a launch keeps no state in the plan's device memory, so both
