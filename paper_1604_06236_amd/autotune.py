@@ -119,7 +119,8 @@ def tune_ragged_prefetch(T, classes=RAGGED_CLASSES, reps=20, verbose=True):
     """For each class of the ragged kernel and each of its three bodies (0 forward, 1 output
     side, 2 adjoint with tap gradient) that has a prefetching form, time a single-class batch
     (per-block taps, about 250 MB per array) with the prefetch on and off and select the faster.
-    Returns {"K,M": [choice per body]} (0 off, 1 on) and every timing."""
+    Returns {"KxM": [choice per body]} (0 off, 1 on; keyed unlike the fused schedules'
+    "K,M" entries, which the library's loader reads) and every timing."""
     import numpy as np
     import torch
     dev = "cuda"
@@ -175,7 +176,7 @@ def tune_ragged_prefetch(T, classes=RAGGED_CLASSES, reps=20, verbose=True):
             if verbose:
                 print(f"ragged ({K}, {M}) body {b}: prefetch {times[1]:.1f} us, without {times[0]:.1f} us "
                       f"-> {'on' if pick else 'off'}", flush=True)
-        choice[f"{K},{M}"] = sel
+        choice[f"{K}x{M}"] = sel
         del S, taps, y, sb, tb
         torch.cuda.empty_cache()
     return choice, report

@@ -22,7 +22,10 @@
 //     output r at a = a1, b = r, c = c1; pass-2 butterfly j reads its input r' at a = r', b = a1,
 //     c = c1.  Both pick their half by the parity of a1, which varies from lane to lane.
 // Pass-1 and pass-2 butterfly j belong to thread j (32 M <= 512 threads); threads past 32 M only
-// take part in pass 0.
+// take part in pass 0.  Since each round into pass 2 delivers the inputs of one parity, pass 2's
+// 32-point DFT runs as 2 x 16: each round's 16 inputs get their twiddles and a 16-point DFT as
+// soon as they arrive, and the two halves are combined with one radix-2 step (the half holding
+// the even inputs is selected per lane by the same bit masks).
 #pragma once
 
 #include "bt_fused.hpp"
@@ -87,7 +90,8 @@ struct HalfThread {
 };
 
 // One block: pass 0 (filter on the input side, length-M DFT), the exchange into pass 1, pass 1
-// (twiddle, length-32 DFT), the exchange into pass 2, pass 2 and the natural-order store.  L
+// (twiddle, length-32 DFT), the exchange into pass 2 with the two 16-point halves of pass 2,
+// their radix-2 combination and the natural-order store.  L
 // holds N/2 points; every thread of the 512 calls it (it contains workgroup barriers).
 // `valid` is false for an empty block slot (its resources have range 0: loads read 0, stores
 // are dropped), whose zero taps do not count.  TAP_NT: streaming cache policy for the taps (per
@@ -106,9 +110,6 @@ __device__ __forceinline__ void half_block(const HalfThread<M> &h, c32 *L, rsrc_
     constexpr bool CONJ = SIDE == SIDE_OUT;
     static_assert(B1 <= 512, "one pass-1 butterfly per thread");
     static_assert(!TGR || SIDE == SIDE_OUT, "tap gradient on the output side only");
-    // the output side holds its taps (and S) next to pass 2's values: sequential twiddle
-    // powers there need fewer registers than the squaring tree
-    constexpr int TWO = SIDE == SIDE_OUT ? OPT_SEQ_TWIDDLE : 0;
     const float Nf = float(N);
     const int t = h.t, j = h.j;
 
@@ -153,7 +154,7 @@ __device__ __forceinline__ void half_block(const HalfThread<M> &h, c32 *L, rsrc_
     });
 
     // ---- pass 1; its outputs in the order the exchange sends them
-    twiddle<TWO, 32>(v, h.w1);
+    twiddle<0, 32>(v, h.w1);
     dft<32>(v);
     c32 x0[16], x1[16];
     static_for<0, 16>([&](auto sI) {
@@ -163,7 +164,12 @@ __device__ __forceinline__ void half_block(const HalfThread<M> &h, c32 *L, rsrc_
     });
 
     // ---- exchange into pass 2: round g carries the outputs r with (r + a1) mod 2 = g and
-    //      the inputs r' with (r' + a1) mod 2 = g
+    //      the inputs r' with (r' + a1) mod 2 = g.  Pass 2's 32-point DFT is split as 2 x 16
+    //      over the input parity: each round's 16 inputs (one parity class) get their twiddles
+    //      w2^{r'} = w2^q (w2^2)^s and a 16-point DFT as soon as they arrive.
+    c32 w2 = h.w2;
+    asm volatile("" : "+v"(w2.x), "+v"(w2.y));
+    const c32 w2sq = cmul(w2, w2);
     c32 z0[16], z1[16];
     static_for<0, 2>([&](auto gI) {
         constexpr int g = decltype(gI)::value;
@@ -177,62 +183,65 @@ __device__ __forceinline__ void half_block(const HalfThread<M> &h, c32 *L, rsrc_
         }
         lds_barrier();
         const int q = g ^ (h.odd_mask & 1);           // parity of this round's r'
+        c32(&zg)[16] = g == 0 ? z0 : z1;
         static_for<0, 16>([&](auto sI) {
             constexpr int s = decltype(sI)::value;
-            const c32 val = lds_get(&L[h.rbase + 16 * M * (2 * s + q)]);
-            if constexpr (g == 0) z0[s] = val;
-            else z1[s] = val;
+            zg[s] = lds_get(&L[h.rbase + 16 * M * (2 * s + q)]);
         });
+        // base w2^q: lanes with q = 1 are those with odd a1 in round 0, even a1 in round 1
+        c32 tw = blend(c32{1.f, 0.f}, w2, g == 0 ? h.odd_mask : ~h.odd_mask);
+        zg[0] = cmul(zg[0], tw);
+        static_for<1, 16>([&](auto sI) {
+            constexpr int s = decltype(sI)::value;
+            tw = cmul(tw, w2sq);
+            zg[s] = cmul(zg[s], tw);
+        });
+        dft<16>(zg);
+        pin(zg);
     });
 
-    // ---- pass 2: twiddle, DFT_32, output side, natural-order store of y[t + B1 r]
-    float tl[1][SIDE == SIDE_OUT && !TGR ? 32 : 1];
-    if constexpr (SIDE == SIDE_OUT && !TGR) {
-        static_for<0, 32>([&](auto rI) {
-            constexpr int r = decltype(rI)::value;
-            tl[0][r] = ld_f<NTT>(rt, uint32_t(j) * FB, r * B1 * FB);
-        });
-    }
+    // ---- pass 2 (rest): combine the two halves, output side, natural-order store of y[t + B1 r]
+    // even inputs: z0 on lanes with even a1, z1 on the others
     c32 z[32];
-    static_for<0, 16>([&](auto sI) {
-        constexpr int s = decltype(sI)::value;
-        z[2 * s] = blend(z0[s], z1[s], h.odd_mask);
-        z[2 * s + 1] = blend(z1[s], z0[s], h.odd_mask);
+    static_for<0, 16>([&](auto kI) {
+        constexpr int k = decltype(kI)::value;
+        const c32 e = blend(z0[k], z1[k], h.odd_mask);
+        const c32 o = rot<k, 32>(blend(z1[k], z0[k], h.odd_mask));
+        z[k] = e + o;
+        z[k + 16] = e - o;
     });
-    twiddle<TWO, 32>(z, h.w2);
-    dft<32>(z);
-    if constexpr (TGR) {
-        // the taps and S in groups of 4 outputs, each group's loads issued after the previous
-        // group's stores (all 32 at once would hold 96 more registers next to z)
-        static_for<0, 8>([&](auto gI) {
+    if constexpr (SIDE == SIDE_OUT) {
+        // the taps (and S) in groups of G outputs, each group's loads issued after the previous
+        // group's stores (all 32 at once would hold 32 (96) more registers next to z)
+        constexpr int G = TGR ? 4 : 8;
+        static_for<0, 32 / G>([&](auto gI) {
             constexpr int g = decltype(gI)::value;
-            float tg[1][4];
-            c32 sv[4];
-            static_for<0, 4>([&](auto rI) {
-                constexpr int r = 4 * g + decltype(rI)::value;
-                tg[0][r - 4 * g] = ld_f<NTT>(rt, uint32_t(j) * FB, r * B1 * FB);
-                sv[r - 4 * g] = ld_c<NTA>(rx, uint32_t(j) * CB, r * B1 * CB);
+            float tg[1][G];
+            c32 sv[TGR ? G : 1];
+            static_for<0, G>([&](auto rI) {
+                constexpr int r = G * g + decltype(rI)::value;
+                tg[0][r - G * g] = ld_f<NTT>(rt, uint32_t(j) * FB, r * B1 * FB);
+                if constexpr (TGR) sv[r - G * g] = ld_c<NTA>(rx, uint32_t(j) * CB, r * B1 * CB);
             });
             tap_factors(tg, div, Nf, zero_tap, [&](int) { return valid && h.has1; });
             if (h.has1) {
-                static_for<0, 4>([&](auto rI) {
-                    constexpr int r = 4 * g + decltype(rI)::value;
+                static_for<0, G>([&](auto rI) {
+                    constexpr int r = G * g + decltype(rI)::value;
                     const c32 w = conj(z[r]);
-                    const c32 s_ = sv[r - 4 * g];
-                    st_f<NTA>(s_.x * w.x + s_.y * w.y, rg, uint32_t(t) * FB, r * B1 * FB);
-                    st_c<NTA>(scale(w, tg[0][r - 4 * g]), ro, uint32_t(t) * CB, r * B1 * CB);
+                    if constexpr (TGR) {
+                        const c32 s_ = sv[r - G * g];
+                        st_f<NTA>(s_.x * w.x + s_.y * w.y, rg, uint32_t(t) * FB, r * B1 * FB);
+                    }
+                    st_c<NTA>(scale(w, tg[0][r - G * g]), ro, uint32_t(t) * CB, r * B1 * CB);
                 });
             }
             asm volatile("" ::: "memory");
         });
     } else {
-        if constexpr (SIDE == SIDE_OUT) tap_factors(tl, div, Nf, zero_tap, [&](int) { return valid && h.has1; });
         if (h.has1) {
             static_for<0, 32>([&](auto rI) {
                 constexpr int r = decltype(rI)::value;
-                c32 w = CONJ ? conj(z[r]) : z[r];
-                if constexpr (SIDE == SIDE_OUT) w = scale(w, tl[0][r]);
-                st_c<NTA>(w, ro, uint32_t(t) * CB, r * B1 * CB);
+                st_c<NTA>(z[r], ro, uint32_t(t) * CB, r * B1 * CB);
             });
         }
     }

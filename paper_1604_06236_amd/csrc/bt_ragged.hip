@@ -233,10 +233,11 @@ __device__ __forceinline__ void ragged_chunk(const RaggedArgs &a, const RaggedIt
                 }
             }
             if (PF && t + 1 < ntiles) fetch(next);
-            // operands of the last pass, fetched while the LDS passes run; where the tap
-            // gradient's operands of the whole last pass would hold more than 48 registers
-            // across the passes (LATE), each iteration of the last pass fetches its own
-            // before its LDS reads instead
+            // operands of the last pass, fetched while the LDS passes run; where the
+            // output side's operands of the whole last pass would hold more than 16 values
+            // per thread across the passes (LATE), each iteration of the last pass fetches
+            // its own taps before its LDS reads instead, and with the tap gradient fetches
+            // its taps and S after its DFT, four outputs at a time
             constexpr bool LATE = SIDE == SIDE_OUT && ITL * RL > 16;
             constexpr bool TL = SIDE == SIDE_OUT && !LATE;
             float tl[TL ? ITL : 1][TL ? RL : 1];
@@ -264,12 +265,10 @@ __device__ __forceinline__ void ragged_chunk(const RaggedArgs &a, const RaggedIt
             for (int i = 0; i < ITL; ++i) {
                 const int j = tid + i * TB;
                 if (FULLL || j < NBL) {
-                    c32 si[LATE && TGR ? RL : 1];
-                    float ti[1][LATE ? RL : 1];
-                    if constexpr (LATE) {
+                    float ti[1][LATE && !TGR ? RL : 1];
+                    if constexpr (LATE && !TGR) {
                         static_for<0, RL>([&](auto rI) {
                             constexpr int q = decltype(rI)::value;
-                            if constexpr (TGR) si[q] = ld_c<NT>(cur.aux, j * CB, q * NSL * CB);
                             ti[0][q] = ld_f<NT>(cur.taps, j * FB, q * NSL * FB);
                         });
                     }
@@ -280,19 +279,41 @@ __device__ __forceinline__ void ragged_chunk(const RaggedArgs &a, const RaggedIt
                     });
                     twiddle<OPT, RL>(v, w1s[SLOTL + i]);
                     dft<RL>(v);
-                    if constexpr (LATE) tap_factors(ti, a.div, Nf, zero_tap, [&](int) { return cur.valid; });
-                    static_for<0, RL>([&](auto rI) {
-                        constexpr int q = decltype(rI)::value;
-                        c32 w = CONJ ? conj(v[q]) : v[q];
-                        if constexpr (LATE) {
-                            if constexpr (TGR) st_f<NT>(si[q].x * w.x + si[q].y * w.y, cur.tg, j * FB, q * NSL * FB);
-                            w = scale(w, ti[0][q]);
-                        } else {
-                            if constexpr (TGR) st_f<NT>(sl[i][q].x * w.x + sl[i][q].y * w.y, cur.tg, j * FB, q * NSL * FB);
-                            if constexpr (SIDE == SIDE_OUT) w = scale(w, tl[i][q]);
-                        }
-                        st_c<NT>(w, cur.out, j * CB, q * NSL * CB);
-                    });
+                    if constexpr (LATE && TGR) {
+                        // the taps and S in groups of 4 outputs after the DFT, each group's loads
+                        // issued after the previous group's stores
+                        static_for<0, RL / 4>([&](auto gI) {
+                            constexpr int g = decltype(gI)::value;
+                            float tg[1][4];
+                            c32 sg[4];
+                            static_for<0, 4>([&](auto rI) {
+                                constexpr int q = 4 * g + decltype(rI)::value;
+                                sg[q - 4 * g] = ld_c<NT>(cur.aux, j * CB, q * NSL * CB);
+                                tg[0][q - 4 * g] = ld_f<NT>(cur.taps, j * FB, q * NSL * FB);
+                            });
+                            tap_factors(tg, a.div, Nf, zero_tap, [&](int) { return cur.valid; });
+                            static_for<0, 4>([&](auto rI) {
+                                constexpr int q = 4 * g + decltype(rI)::value;
+                                const c32 w = conj(v[q]);
+                                st_f<NT>(sg[q - 4 * g].x * w.x + sg[q - 4 * g].y * w.y, cur.tg, j * FB, q * NSL * FB);
+                                st_c<NT>(scale(w, tg[0][q - 4 * g]), cur.out, j * CB, q * NSL * CB);
+                            });
+                            asm volatile("" ::: "memory");
+                        });
+                    } else {
+                        if constexpr (LATE) tap_factors(ti, a.div, Nf, zero_tap, [&](int) { return cur.valid; });
+                        static_for<0, RL>([&](auto rI) {
+                            constexpr int q = decltype(rI)::value;
+                            c32 w = CONJ ? conj(v[q]) : v[q];
+                            if constexpr (LATE) {
+                                w = scale(w, ti[0][q]);
+                            } else {
+                                if constexpr (TGR) st_f<NT>(sl[i][q].x * w.x + sl[i][q].y * w.y, cur.tg, j * FB, q * NSL * FB);
+                                if constexpr (SIDE == SIDE_OUT) w = scale(w, tl[i][q]);
+                            }
+                            st_c<NT>(w, cur.out, j * CB, q * NSL * CB);
+                        });
+                    }
                 }
             }
         }

@@ -29,7 +29,7 @@ def load_schedules(path: Optional[str] = None) -> bool:
     """Apply autotuned schedule choices from a JSON file ($BT_SCHEDULES, or
     schedules.json next to this module): per-(K, M) schedules go to the library,
     the ragged work-item size ("ragged_chunk_tiles") to RaggedPlan and the ragged
-    per-class prefetch choices ("ragged_prefetch": {"K,M": [forward, output side,
+    per-class prefetch choices ("ragged_prefetch": {"KxM": [forward, output side,
     tap gradient]}, 0 off / 1 on) to the library.  Returns True when a file was
     applied."""
     import json
@@ -44,7 +44,7 @@ def load_schedules(path: Optional[str] = None) -> bool:
             sel = json.load(f)
         _RAGGED_CHUNK = int(sel.get("ragged_chunk_tiles", 0))
         for km, bodies in sel.get("ragged_prefetch", {}).items():
-            K, M = (int(v) for v in km.split(","))
+            K, M = (int(v) for v in km.split("x"))
             for body, on in enumerate(bodies):
                 # a choice this build cannot honour (no such class or body) keeps the default
                 nat.load().transform_ragged_prefetch_select(K, M, body, int(on))

@@ -106,6 +106,31 @@ def test_schedule_registry(lib, tmp_path):
     assert lib.transform_schedule_select(128, 15, -1, 0) == nat.TF_OK
 
 
+def test_package_schedules_load_as_written(lib):
+    """The library's loader applies exactly the fused "K,M": [schedule, grid cap] entries of
+    the package's schedules.json; the other keys (the ragged kernel's options) leave every
+    other shape's selection alone."""
+    import ctypes
+    import json
+    import os
+    path = os.path.join(os.path.dirname(nat.__file__), "schedules.json")
+    sel = json.load(open(path))
+    fused = {tuple(int(v) for v in k.split(",")): v for k, v in sel.items() if "," in k}
+    assert fused and all(isinstance(v, list) and len(v) == 2 for v in fused.values())
+    shapes = [(K, M) for K in (1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024) for M in range(1, 17)]
+    i, c = ctypes.c_int32(), ctypes.c_int32()
+
+    def selected(K, M):
+        assert lib.transform_schedule_selected(K, M, ctypes.byref(i), ctypes.byref(c)) == nat.TF_OK
+        return [i.value, c.value]
+    for K, M in shapes:
+        assert lib.transform_schedule_select(K, M, -1, 0) == nat.TF_OK
+    before = {km: selected(*km) for km in shapes}
+    assert lib.transform_load_schedule(path.encode()) == nat.TF_OK
+    for km in shapes:
+        assert selected(*km) == (fused[km] if km in fused else before[km]), km
+
+
 def test_ragged_prefetch_registry(lib):
     """Per-class tile-pipelining choices of the ragged kernel: host-side table only."""
     import ctypes
