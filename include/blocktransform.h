@@ -236,10 +236,13 @@ typedef struct tf_ragged_plan_s *tf_ragged_plan;
 int transform_ragged_plan_create(const int32_t *K, const int32_t *M, const int64_t *x_off,
                                  const int64_t *tap_off, int64_t nblocks, int64_t total_points,
                                  tf_ragged_plan *plan);
-/* The same with an explicit work-item size: each item is `chunk_tiles` tiles
-   (a tile fills one workgroup with blocks of one class); 0 picks four.  Larger
-   items pipeline more tiles through each workgroup, smaller ones balance
-   better; the autotuner chooses. */
+/* The same with an explicit work-item size: each item is up to `chunk_tiles`
+   tiles (a tile fills one workgroup with blocks of one class); 0 picks four.
+   Larger items pipeline more tiles through each workgroup, smaller ones balance
+   better; the autotuner chooses.  Whatever the value, no item carries more than a
+   quarter of one workgroup slot's share of the batch's points (slots: the
+   device's CUs times two), so classes of large blocks may get fewer tiles per
+   item, down to one. */
 int transform_ragged_plan_create_ex(const int32_t *K, const int32_t *M, const int64_t *x_off,
                                     const int64_t *tap_off, int64_t nblocks, int64_t total_points,
                                     int32_t chunk_tiles, tf_ragged_plan *plan);

@@ -639,9 +639,12 @@ extern "C" int transform_ragged_plan_create_ex(const int32_t *K, const int32_t *
         if (x_off[b] < 0 || x_off[b] + N > total_points || tap_off[b] < 0) return TF_EINVAL;
         members[f->second].push_back(int(b));
     }
-    // work items of `chunk_tiles` tiles of same-class blocks, sorted by cost (largest
+    // work items of up to `chunk_tiles` tiles of same-class blocks, sorted by cost (largest
     // first); 0 picks four (each tile after the first has its inputs fetched while the
-    // previous one runs)
+    // previous one runs).  No item carries more than a quarter of one workgroup slot's fair
+    // share of the batch's points (slots: CUs x two workgroups), or the largest items, which
+    // start first, would set the length of the launch; classes of large blocks get fewer
+    // tiles per item (at least one).
     int max_lds = 0;
     for (int c = 0; c < ncls; ++c)
         if (!members[c].empty()) max_lds = std::max(max_lds, cls[c].lds);
@@ -654,9 +657,18 @@ extern "C" int transform_ragged_plan_create_ex(const int32_t *K, const int32_t *
         std::lock_guard<std::mutex> lk(g_pf_mu);
         for (int c = 0; c < ncls; ++c) pf[c] = pf_bits(c);
     }
+    int ncu = 0, cur_dev = 0;
+    if (hipGetDevice(&cur_dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, cur_dev) != hipSuccess || ncu < 1)
+        ncu = 256;
+    double total_pts = 0;
+    for (int c = 0; c < ncls; ++c) total_pts += double(members[c].size()) * cls[c].N;
+    const double item_cap = total_pts / (double(ncu) * 2.0 * 4.0);
     for (int c = 0; c < ncls; ++c) {
         if (members[c].empty()) continue;
-        const size_t per_chunk = size_t(cls[c].BPW) * chunk_tiles;
+        const double tile_pts = double(cls[c].BPW) * cls[c].N;
+        const int tiles = int(std::max(1.0, std::min(double(chunk_tiles), std::floor(item_cap / tile_pts))));
+        const size_t per_chunk = size_t(cls[c].BPW) * tiles;
         for (size_t s = 0; s < members[c].size(); s += per_chunk) {
             RaggedItem it{};
             it.cls = c;
