@@ -43,6 +43,7 @@ TOL = 1e-5
 KERNEL_SOURCES = {
     "ragged": ("bt_ragged.hip", "bt_half.hpp", "bt_fused.hpp", "bt_dft.hpp"),
     "fused": ("bt_fused.hpp", "bt_dft.hpp"),
+    "fused_half": ("bt_fused_half.hip", "bt_half.hpp", "bt_fused.hpp", "bt_dft.hpp"),
 }
 PROFILE_WORKLOADS = ("ragged", "ragged_class", "plain_gpu", "precision", "split_bf16", "split_fp16",
                      "differentiation", "decimated", "nufft", "schedules", "copy")
@@ -312,12 +313,15 @@ def uniform_workload(T, W, cfg, args, nbuf, tapgrad=False, rocfft=False, roof_na
     fwd_bytes = 16.0 * B * N + 4.0 * N
     step_bytes = 2 * fwd_bytes + (8.0 * B * N if tapgrad else 0.0)
     sched = T.selected_schedule(K, M)
+    half = bool(sched[2].get("half_lds"))
+    kind = "fused_half" if half else "fused"
     res = {"blocks_per_s": round(B / t, 1), "ms_per_step": round(t * 1e3, 4),
            "achieved_GBps": round(step_bytes / t / 1e9, 1),
            "frac_hbm_peak": round(step_bytes / t / 1e9 / HBM_PEAK_GBS, 4),
            "roofline": _roofline(fwd_bytes, fwd_ms,
-                                 measured_traffic(roof_name, "fused", sched[:2]) if roof_name else None,
-                                 "fused_kernel (forward), schedule %s" % json.dumps(sched[2]),
+                                 measured_traffic(roof_name, kind, sched[:2]) if roof_name else None,
+                                 "%s (forward), schedule %s" % ("half_lds_kernel" if half else "fused_kernel",
+                                                                json.dumps(sched[2])),
                                  {"adjoint_kernel_ms": round(adj_ms, 5)})}
     # error of the timed data on a seeded sample against the O(N^2) sums
     S0, y0, yb0, sb0 = sets[0]

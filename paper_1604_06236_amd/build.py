@@ -37,7 +37,8 @@ def _headers_mtime():
 # translation units whose kernels stage data in LDS: the test build that poisons LDS
 # (-DBT_POISON_LDS, libblocktransform_poison.so) recompiles these and reuses the others
 POISON_SOURCES = ("bt_fused_m01_04.hip", "bt_fused_m05_08.hip", "bt_fused_m09_12.hip",
-                  "bt_fused_m13_16.hip", "bt_fused_tuned.hip", "bt_ragged.hip", "bt_decimated.hip")
+                  "bt_fused_m13_16.hip", "bt_fused_tuned.hip", "bt_fused_half.hip", "bt_ragged.hip",
+                  "bt_decimated.hip")
 POISON_LIB = os.path.join(PKG, "libblocktransform_poison.so")
 
 

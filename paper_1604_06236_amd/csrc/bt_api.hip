@@ -23,6 +23,7 @@ void register_fused_m05_08(std::vector<FusedEntry> &v);
 void register_fused_m09_12(std::vector<FusedEntry> &v);
 void register_fused_m13_16(std::vector<FusedEntry> &v);
 void register_fused_tuned(std::vector<FusedEntry> &v);
+void register_fused_half(std::vector<FusedEntry> &v);
 
 thread_local std::string g_last_error;
 
@@ -46,6 +47,7 @@ static Registry &registry()
         register_fused_m09_12(g->entries);
         register_fused_m13_16(g->entries);
         register_fused_tuned(g->entries);
+        register_fused_half(g->entries);
         for (int i = 0; i < (int)g->entries.size(); ++i)
             g->by_km[{g->entries[i].K, g->entries[i].M}].push_back(i);
         return g;
@@ -590,10 +592,12 @@ extern "C" int transform_schedule_describe(int32_t K, int32_t M, int32_t idx, ch
     std::snprintf(buf, buflen,
                   "{\"K\": %d, \"M\": %d, \"radices\": [%s], \"threads_per_block\": %d, "
                   "\"blocks_per_workgroup\": %d, \"lds_bytes\": %d, \"prefetch\": %s, "
-                  "\"sequential_twiddles\": %s, \"paired_io\": %s, \"nontemporal\": %s, \"early_fetch\": %s}",
+                  "\"sequential_twiddles\": %s, \"paired_io\": %s, \"nontemporal\": %s, \"early_fetch\": %s, "
+                  "\"half_lds\": %s}",
                   e.K, e.M, rad.c_str(), e.TB, e.BPW, e.lds_bytes, (e.opt & OPT_NO_PREFETCH) ? "false" : "true",
                   (e.opt & OPT_SEQ_TWIDDLE) ? "true" : "false", (e.opt & OPT_PAIRED_IO) ? "true" : "false",
-                  (e.opt & OPT_NT) ? "true" : "false", (e.opt & OPT_EARLY_FETCH) ? "true" : "false");
+                  (e.opt & OPT_NT) ? "true" : "false", (e.opt & OPT_EARLY_FETCH) ? "true" : "false",
+                  (e.opt & OPT_HALF_LDS) ? "true" : "false");
     return TF_OK;
 }
 

@@ -117,7 +117,7 @@ def test_inverse_adjoint(T, K, M, shared):
 
 def test_all_schedules_agree(T):
     """Every compiled schedule of the standard shapes meets the bar."""
-    for K, M in ((16, 5), (128, 15), (256, 9), (1024, 15)):
+    for K, M in ((16, 5), (128, 15), (256, 9), (1024, 15), (1024, 9), (1024, 3)):
         B = 19
         S, taps = _inputs(B, K, M, seed=K)
         y_ref = O.forward(S, taps)
@@ -290,6 +290,36 @@ def test_per_block_taps_partial_group_leaves_status_clear(T, K, M):
             assert int(st.item()) == 1, (K, M, i)
         finally:
             T.select_schedule(K, M, -1)
+
+
+@pytest.mark.parametrize("M", [15, 9])
+def test_half_lds_schedules_per_block_taps(T, M):
+    """The half-block exchange schedules of (1024, M) with per-block taps (streamed) under a
+    capped grid: forward, inverse and adjoint against the oracle; the inverse's zero-tap status
+    stays clear for nonzero taps and is set by one zero tap in the last block."""
+    import torch
+    K, B = 1024, 11
+    N = K * M
+    idx = [i for i, d in enumerate(T.schedules(K, M)) if d.get("half_lds")]
+    assert len(idx) == 1 and T.schedules(K, M)[idx[0]]["lds_bytes"] == N * 4
+    S, taps = _inputs(B, K, M, seed=M, shared=False)
+    y = W.cn01(np.random.default_rng(M + 1), (B, N)).astype(np.complex64)
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    print(f"case half schedule K={K} M={M} idx={idx[0]}", flush=True)
+    try:
+        T.select_schedule(K, M, idx[0], grid_cap=3)
+        assert rel_l2(_host(T.transform_forward(_dev(S), _dev(taps), K, M)), O.forward(S, taps)) < TOL
+        inv = _host(T.transform_inverse(_dev(y), _dev(taps), K, M, status=st))
+        assert rel_l2(inv, O.inverse(y, taps)) < TOL and int(st.item()) == 0
+        sb = _host(T.transform_adjoint(_dev(y), _dev(taps), K, M)[0])
+        assert rel_l2(sb, O.adjoint(y, taps)[0]) < TOL
+        t2 = taps.copy()
+        t2[B - 1, N - 1] = 0.0
+        st.zero_()
+        T.transform_inverse(_dev(y), _dev(t2), K, M, status=st)
+        assert int(st.item()) == 1
+    finally:
+        T.select_schedule(K, M, -1, grid_cap=0)
 
 
 def test_empty_and_errors(T):

@@ -71,6 +71,37 @@ def test_poisoned_fused_at_benchmark_shapes(env):
         assert rel(yh[idx], O.forward(S[idx], taps)) < TOL
 
 
+def test_poisoned_half_lds_schedules(env):
+    """Every (1024, M) half-block exchange schedule with its LDS prefilled with NaN: a missing
+    barrier between an exchange round's writes and reads would let NaN through."""
+    torch, lib = env
+    from paper_1604_06236_amd import transform as T
+    lib.transform_schedule_select.argtypes = [ctypes.c_int32] * 4
+    for M in (3, 9, 15):
+        K, B = 1024, 37
+        idx = [i for i, d in enumerate(T.schedules(K, M)) if d.get("half_lds")]
+        assert idx, M
+        rng = np.random.default_rng(M)
+        S = W.cn01(rng, (B, K * M)).astype(np.complex64)
+        taps = W.rc_taps(K * M, 0.3).astype(np.float32)
+        yb = W.cn01(rng, (B, K * M)).astype(np.complex64)
+        dS, dt, dyb = (torch.from_numpy(x).cuda() for x in (S, taps, yb))
+        y, sb = torch.empty_like(dS), torch.empty_like(dS)
+        print(f"case poison half K={K} M={M} schedule={idx[0]}", flush=True)
+        try:
+            assert lib.transform_schedule_select(K, M, idx[0], 5) == 0      # several blocks per workgroup
+            assert lib.transform_forward(_p(dS), _p(dt), _p(y), B, K, M, 0, 0, None, 0, _s(torch)) == 0
+            assert lib.transform_adjoint(_p(dyb), _p(dt), None, _p(sb), None, B, K, M, 0, 0, None, 0,
+                                         _s(torch)) == 0
+            torch.cuda.synchronize()
+        finally:
+            lib.transform_load_schedule(os.path.join(PKG, "schedules.json").encode())
+        yh, sbh = y.cpu().numpy(), sb.cpu().numpy()
+        assert np.all(np.isfinite(yh)) and np.all(np.isfinite(sbh))
+        assert rel(yh, F.forward(S, taps)) < TOL
+        assert rel(sbh, F.adjoint(yb, taps)[0]) < TOL
+
+
 def test_poisoned_decimated(env):
     torch, lib = env
     c = W.CONFIGS["plain_gpu"]
