@@ -295,8 +295,9 @@ def test_per_block_taps_partial_group_leaves_status_clear(T, K, M):
 @pytest.mark.parametrize("M", [15, 9])
 def test_half_lds_schedules_per_block_taps(T, M):
     """The half-block exchange schedules of (1024, M) with per-block taps (streamed) under a
-    capped grid: forward, inverse and adjoint against the oracle; the inverse's zero-tap status
-    stays clear for nonzero taps and is set by one zero tap in the last block."""
+    capped grid: forward, inverse, adjoint and the inverse's adjoint against the oracle; the
+    inverse's zero-tap status stays clear for nonzero taps and is set by one zero tap in the
+    last block."""
     import torch
     K, B = 1024, 11
     N = K * M
@@ -313,6 +314,8 @@ def test_half_lds_schedules_per_block_taps(T, M):
         assert rel_l2(inv, O.inverse(y, taps)) < TOL and int(st.item()) == 0
         sb = _host(T.transform_adjoint(_dev(y), _dev(taps), K, M)[0])
         assert rel_l2(sb, O.adjoint(y, taps)[0]) < TOL
+        g = _host(T.transform_inverse_adjoint(_dev(y), _dev(taps), K, M)[0])
+        assert rel_l2(g, O.inverse_adjoint(y, taps)[0]) < TOL
         t2 = taps.copy()
         t2[B - 1, N - 1] = 0.0
         st.zero_()
